@@ -1,0 +1,311 @@
+"""Seeded synthetic inputs: island meshes, materials, head-field schedules and design batches.
+
+This module produces *inputs* only.  It holds none of the method's arithmetic: no finite-element
+quantities, no fields, no time stepping.  Both the GPU library (through its Python binding) and
+the CPU oracle consume exactly the arrays it returns, so that a parity test compares two
+independent solvers on the same bytes.
+
+Geometry follows the media description of the paper (Sec. II.B and Fig. 3): a cylindrical or
+elliptic exchange-coupled-composite island, soft layer on top (nearest the head, which is the
+reading that makes "9 nm below the air bearing surface is the middle of the soft phase" in
+Sec. III consistent with the 6 nm spacing), hard layer below, both easy axes along z.  The paper
+meshes with NETGEN; here a seeded extruded mesher stands in for it:
+
+* a 2-D Delaunay triangulation of boundary samples plus a jittered hexagonal interior lattice,
+* extruded into z-levels (the soft/hard interface is a level),
+* each prism cut into three tetrahedra by a rule that depends only on the global 2-D node
+  indices, which keeps neighbouring prisms conforming,
+* interface nodes duplicated: the soft copy and the hard copy carry the same coordinates and are
+  listed as pairs, so each node belongs to exactly one layer.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from scipy.spatial import Delaunay
+
+NM = 1e-9
+
+# Field kinds understood by both solvers.
+FIELD_UNIFORM = 0
+FIELD_POLE = 1
+
+LAYER_SOFT = 0
+LAYER_HARD = 1
+
+
+@dataclasses.dataclass
+class Mesh:
+    """P1 tetrahedral island mesh (SI units)."""
+    xyz: np.ndarray          # [3][n] float64, metres
+    tet: np.ndarray          # [ntet][4] int32, positively oriented
+    layer: np.ndarray        # [n] int32, 0 = soft (top), 1 = hard (bottom)
+    iface: np.ndarray        # [nif][2] int32, (soft node, hard node) with equal coordinates
+    n2d: int = 0             # 2-D nodes per level (informational)
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[1])
+
+    @property
+    def ntet(self) -> int:
+        return int(self.tet.shape[0])
+
+
+@dataclasses.dataclass
+class Material:
+    """Per-instance material: index 0 = soft layer, 1 = hard layer (SI)."""
+    Ms: tuple = (1.0e6, 0.6e6)          # A/m
+    K: tuple = (0.2e6, 1.2e6)           # J/m^3
+    A: tuple = (10e-12, 10e-12)         # J/m
+    axis: tuple = ((0.0, 0.0, 1.0), (0.0, 0.0, 1.0))
+    A_int: float = 3e-12                # J/m, interlayer exchange constant
+    delta_int: float = 1e-9             # m, interlayer thickness
+    alpha: float = 0.1
+
+
+@dataclasses.dataclass
+class Field:
+    """Applied-field schedule (tesla, seconds, metres).
+
+    kind = FIELD_UNIFORM:  B(t) = B_peak * r(t) * dir + B_ext
+    kind = FIELD_POLE:     B(x, t) = B_peak * r(t) * fx(x - x_off - v t) * fy(y - y_off - v_y t) * dir + B_ext
+    with r(t) = min(t / t_rise, 1).
+    """
+    kind: int = FIELD_UNIFORM
+    B_peak: float = 1.2
+    dir: tuple = (0.0, 0.0, -1.0)
+    t_rise: float = 0.1e-9
+    v: tuple = (0.0, 0.0, 0.0)
+    x_off: tuple = (0.0, 0.0, 0.0)
+    L_grad: float = 10e-9
+    W_pole: float = 13e-9
+    B_ext: tuple = (0.0, 0.0, 0.0)
+
+
+# ----------------------------------------------------------------------------------------------
+# 2-D triangulation of an ellipse
+# ----------------------------------------------------------------------------------------------
+
+def _ellipse_boundary(a: float, b: float, h: float) -> np.ndarray:
+    """Points on the ellipse x^2/a^2 + y^2/b^2 = 1 at (almost) equal arc-length spacing ~h."""
+    th = np.linspace(0.0, 2.0 * np.pi, 4097)
+    x, y = a * np.cos(th), b * np.sin(th)
+    seg = np.hypot(np.diff(x), np.diff(y))
+    s = np.concatenate([[0.0], np.cumsum(seg)])
+    perim = s[-1]
+    nb = max(6, int(round(perim / h)))
+    targets = np.arange(nb) * perim / nb
+    tq = np.interp(targets, s, th)
+    return np.stack([a * np.cos(tq), b * np.sin(tq)], axis=1)
+
+
+def _disk_points(a: float, b: float, h: float, rng: np.random.Generator, jitter: float):
+    bnd = _ellipse_boundary(a, b, h)
+    dy = h * math.sqrt(3.0) / 2.0
+    pts = []
+    ny = int(math.ceil(b / dy)) + 1
+    nx = int(math.ceil(a / h)) + 1
+    for j in range(-ny, ny + 1):
+        y = j * dy
+        off = 0.5 * h if (j % 2) else 0.0
+        for i in range(-nx, nx + 1):
+            x = i * h + off
+            if (x / a) ** 2 + (y / b) ** 2 >= 1.0:
+                continue
+            pts.append((x, y))
+    inner = np.array(pts, dtype=np.float64).reshape(-1, 2)
+    if inner.shape[0]:
+        d = np.min(np.hypot(inner[:, None, 0] - bnd[None, :, 0], inner[:, None, 1] - bnd[None, :, 1]), axis=1)
+        inner = inner[d >= 0.6 * h]
+    if inner.shape[0]:
+        inner = inner + rng.uniform(-jitter * h, jitter * h, size=inner.shape)
+    return bnd, inner
+
+
+def _triangulate(a: float, b: float, h: float, seed: int, jitter: float):
+    rng = np.random.default_rng(seed)
+    bnd, inner = _disk_points(a, b, h, rng, jitter)
+    p2 = np.concatenate([bnd, inner], axis=0) if inner.shape[0] else bnd
+    tri = Delaunay(p2).simplices.astype(np.int64)
+    # drop slivers that Delaunay may create between nearly collinear boundary samples
+    e1 = p2[tri[:, 1]] - p2[tri[:, 0]]
+    e2 = p2[tri[:, 2]] - p2[tri[:, 0]]
+    area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+    tri = tri[area > 1e-3 * h * h]
+    used = np.unique(tri)
+    remap = -np.ones(p2.shape[0], dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return p2[used], remap[tri]
+
+
+# ----------------------------------------------------------------------------------------------
+# Extrusion
+# ----------------------------------------------------------------------------------------------
+
+def _levels(t: float, hz: float) -> np.ndarray:
+    nl = max(1, int(round(t / hz)))
+    return np.linspace(0.0, t, nl + 1)
+
+
+def island_mesh(a: float, b: float, t_soft: float, t_hard: float, h: float, seed: int = 0,
+                jitter: float = 0.15) -> Mesh:
+    """Extruded ECC island: hard layer z in [0, t_hard], soft layer z in [t_hard, t_hard+t_soft].
+
+    a, b are the semi-axes (a = b for a cylinder); h is the target edge length.
+    """
+    p2, tri = _triangulate(a, b, h, seed, jitter)
+    n2 = p2.shape[0]
+    zh = _levels(t_hard, h)
+    zs = t_hard + _levels(t_soft, h)
+    levels = [(z, LAYER_HARD) for z in zh] + [(z, LAYER_SOFT) for z in zs]
+    nlev = len(levels)
+    n = nlev * n2
+    xyz = np.empty((3, n), dtype=np.float64)
+    layer = np.empty(n, dtype=np.int32)
+    for k, (z, L) in enumerate(levels):
+        xyz[0, k * n2:(k + 1) * n2] = p2[:, 0]
+        xyz[1, k * n2:(k + 1) * n2] = p2[:, 1]
+        xyz[2, k * n2:(k + 1) * n2] = z
+        layer[k * n2:(k + 1) * n2] = L
+    tri_sorted = np.sort(tri, axis=1)
+    tets = []
+    nh = len(zh)
+    # cells inside the hard block: levels 0..nh-1; inside the soft block: levels nh..nlev-1
+    for k in range(nlev - 1):
+        if k == nh - 1:
+            continue  # the interface: no cells between the duplicated planes
+        lo, hi = k * n2, (k + 1) * n2
+        v0, v1, v2 = tri_sorted[:, 0], tri_sorted[:, 1], tri_sorted[:, 2]
+        B0, B1, B2 = lo + v0, lo + v1, lo + v2
+        T0, T1, T2 = hi + v0, hi + v1, hi + v2
+        tets.append(np.stack([B0, B1, B2, T2], axis=1))
+        tets.append(np.stack([B0, B1, T1, T2], axis=1))
+        tets.append(np.stack([B0, T0, T1, T2], axis=1))
+    tet = np.concatenate(tets, axis=0).astype(np.int64)
+    # orient positively
+    P = xyz.T
+    d1 = P[tet[:, 1]] - P[tet[:, 0]]
+    d2 = P[tet[:, 2]] - P[tet[:, 0]]
+    d3 = P[tet[:, 3]] - P[tet[:, 0]]
+    det = np.einsum("ij,ij->i", d1, np.cross(d2, d3))
+    neg = det < 0
+    tet[neg, 2], tet[neg, 3] = tet[neg, 3].copy(), tet[neg, 2].copy()
+    iface = np.stack([nh * n2 + np.arange(n2), (nh - 1) * n2 + np.arange(n2)], axis=1)
+    return Mesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet.astype(np.int32)),
+                layer=layer, iface=np.ascontiguousarray(iface.astype(np.int32)), n2d=n2)
+
+
+def island_mesh_target(a: float, b: float, t_soft: float, t_hard: float, n_target: int,
+                       seed: int = 0, tol: float = 0.12) -> Mesh:
+    """Mesh whose node count is within `tol` of n_target (bisection on the edge length)."""
+    vol = math.pi * a * b * (t_soft + t_hard)
+    h = (vol / n_target) ** (1.0 / 3.0)
+    lo, hi = 0.3 * h, 3.0 * h
+    best = None
+    for _ in range(40):
+        m = island_mesh(a, b, t_soft, t_hard, h, seed)
+        err = m.n / n_target - 1.0
+        if best is None or abs(err) < abs(best[0]):
+            best = (err, m)
+        if abs(err) <= tol:
+            return m
+        if m.n > n_target:
+            lo = h
+        else:
+            hi = h
+        h = 0.5 * (lo + hi)
+    return best[1]
+
+
+# ----------------------------------------------------------------------------------------------
+# Workloads
+# ----------------------------------------------------------------------------------------------
+
+def single_island_workload(seed: int = 0, n_target: int = 500):
+    """A single two-layer cylinder: d = 8 nm, t = 10 nm (soft 3 nm on top, hard 7 nm),
+    uniform field 30 degrees from -z ramped 0 -> 1.2 T in 0.1 ns, alpha = 0.1."""
+    mesh = island_mesh_target(4 * NM, 4 * NM, 3 * NM, 7 * NM, n_target, seed=seed)
+    mat = Material()
+    psi = math.radians(30.0)
+    fld = Field(kind=FIELD_UNIFORM, B_peak=1.2, dir=(math.sin(psi), 0.0, -math.cos(psi)),
+                t_rise=0.1e-9)
+    return mesh, mat, fld
+
+
+def patch_workload(seed: int = 1, n_target: int = 2000, sigma_rel: float = 0.05):
+    """3x3 patch of elliptic islands (18 x 4.5 nm, t = 10 nm), 25 nm down-track by 6.5 nm
+    cross-track pitch, per-island per-layer Ms and K scaled by (1 + 0.05 N(0,1)), analytic
+    pole field 1.5 T, gradient length 10 nm, 20 m/s, rise 0.1 ns.
+
+    Returns (mesh, [Material]*9, [Field]*9, offsets[9][3]).
+    """
+    mesh = island_mesh_target(9 * NM, 2.25 * NM, 3 * NM, 7 * NM, n_target, seed=seed)
+    rng = np.random.default_rng(seed)
+    base = Material()
+    mats, flds, offs = [], [], []
+    px, py = 25 * NM, 6.5 * NM
+    psi = math.radians(20.0)
+    for i in range(3):
+        for j in range(3):
+            sc = 1.0 + sigma_rel * rng.standard_normal(4)
+            mats.append(dataclasses.replace(
+                base, Ms=(base.Ms[0] * sc[0], base.Ms[1] * sc[1]),
+                K=(base.K[0] * sc[2], base.K[1] * sc[3])))
+            offs.append(((i - 1) * px, (j - 1) * py, 0.0))
+    for _ in range(9):
+        flds.append(Field(kind=FIELD_POLE, B_peak=1.5, dir=(math.sin(psi), 0.0, -math.cos(psi)),
+                          t_rise=0.1e-9, v=(20.0, 0.0, 0.0), x_off=(-10 * NM, 0.0, 0.0),
+                          L_grad=10 * NM, W_pole=2 * py))
+    return mesh, mats, flds, np.array(offs, dtype=np.float64)
+
+
+# Design-vector layout used by the batched designs and the surrogate:
+DESIGN_NAMES = ("d", "t_soft", "t_hard", "Ms_soft", "Ms_hard", "K_soft", "K_hard", "A_int",
+                "psi", "B_peak", "alpha", "t_rise")
+DESIGN_LO = np.array([6e-9, 2e-9, 2e-9, 0.4e6, 0.4e6, 0.1e6, 0.1e6, 0.5e-12, 0.0, 0.8, 0.02,
+                      0.05e-9])
+DESIGN_HI = np.array([12e-9, 8e-9, 8e-9, 1.2e6, 1.2e6, 1.5e6, 1.5e6, 10e-12,
+                      math.radians(45.0), 2.0, 0.2, 0.2e-9])
+
+
+def sample_designs(n: int, seed: int = 2, fixed_alpha_rise: bool = True) -> np.ndarray:
+    """Uniform designs in the batched-island ranges; returns [n][12] float64.
+
+    With fixed_alpha_rise the last two entries are alpha = 0.1 and t_rise = 0.1 ns (the ranges
+    of the batched-island workload do not include them)."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n, len(DESIGN_NAMES)))
+    x = DESIGN_LO + (DESIGN_HI - DESIGN_LO) * u
+    if fixed_alpha_rise:
+        x[:, 10] = 0.1
+        x[:, 11] = 0.1e-9
+    return x
+
+
+def design_node_target(x: np.ndarray, density: float = 1.0e27) -> int:
+    """Node count proportional to island volume (1 node per nm^3), clipped to [300, 3000]."""
+    vol = math.pi * (x[0] / 2) ** 2 * (x[1] + x[2])
+    return int(min(3000, max(300, round(density * vol))))
+
+
+def design_inputs(x: np.ndarray, seed: int = 0):
+    """(mesh, Material, Field) for one design vector x (see DESIGN_NAMES)."""
+    r = 0.5 * x[0]
+    mesh = island_mesh_target(r, r, x[1], x[2], design_node_target(x), seed=seed)
+    mat = Material(Ms=(x[3], x[4]), K=(x[5], x[6]), A_int=x[7], alpha=x[10])
+    psi = x[8]
+    fld = Field(kind=FIELD_UNIFORM, B_peak=x[9], dir=(math.sin(psi), 0.0, -math.cos(psi)),
+                t_rise=x[11])
+    return mesh, mat, fld
+
+
+def random_unit_m(n: int, seed: int, cone: float = math.pi) -> np.ndarray:
+    """[3][n] unit vectors within `cone` radians of +z (seeded)."""
+    rng = np.random.default_rng(seed)
+    ct = 1.0 - (1.0 - math.cos(cone)) * rng.random(n)
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    ph = 2.0 * math.pi * rng.random(n)
+    return np.ascontiguousarray(np.stack([st * np.cos(ph), st * np.sin(ph), ct]))

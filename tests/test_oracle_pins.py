@@ -1,0 +1,478 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Every check here is independent of the oracle's own formulas: closed forms, invariants, brute
+force through a different route, published worked numbers (tests/golden/).
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from paper_1603_09493_amd import inputs as I
+
+MU0 = 4e-7 * math.pi
+GAMMA = 1.76085963023e11
+
+
+def _golden(name):
+    rows = []
+    for line in open(f"{__file__.rsplit('/', 1)[0]}/golden/{name}"):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+# ------------------------------------------------------------------------------------------
+# tiny hand-built meshes
+# ------------------------------------------------------------------------------------------
+
+def _mesh_from(xyz, tets, layer=None, iface=None):
+    xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).T)
+    tets = np.asarray(tets, dtype=np.int32)
+    n = xyz.shape[1]
+    # orient positively
+    P = xyz.T
+    for t in tets:
+        d = np.dot(P[t[1]] - P[t[0]], np.cross(P[t[2]] - P[t[0]], P[t[3]] - P[t[0]]))
+        if d < 0:
+            t[2], t[3] = t[3], t[2]
+    layer = np.zeros(n, np.int32) if layer is None else np.asarray(layer, np.int32)
+    iface = np.zeros((0, 2), np.int32) if iface is None else np.asarray(iface, np.int32)
+    return I.Mesh(xyz=xyz, tet=tets, layer=layer, iface=iface)
+
+
+def _cube5(s=1e-9, shift=(0, 0, 0)):
+    """Unit cube of edge s split into 5 tets (one central, four corners)."""
+    c = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0], [0, 0, 1], [1, 0, 1], [0, 1, 1],
+                  [1, 1, 1]], dtype=np.float64) * s + np.asarray(shift)
+    tets = [[0, 1, 2, 4], [1, 3, 2, 7], [1, 4, 5, 7], [2, 4, 6, 7], [1, 2, 4, 7]]
+    return c, tets
+
+
+def _bary_grad(P):
+    """Gradients of the barycentric functions by inverting [1 x y z] (a route independent of the
+    edge cross products the oracle uses)."""
+    A = np.hstack([np.ones((4, 1)), P])
+    Ainv = np.linalg.inv(A)          # column a holds the coefficients of phi_a
+    return Ainv[1:, :].T, abs(np.linalg.det(A)) / 6.0
+
+
+# ------------------------------------------------------------------------------------------
+# P1 assembly
+# ------------------------------------------------------------------------------------------
+
+def test_single_tet_brute_force(oracle_mod):
+    rng = np.random.default_rng(0)
+    P = rng.random((4, 3)) * 1e-9
+    mesh = _mesh_from(P, [[0, 1, 2, 3]])
+    om = oracle_mod.OracleMesh(mesh)
+    e = om.export()
+    Pm = mesh.xyz.T
+    g, V = _bary_grad(Pm[mesh.tet[0]])
+    assert abs(e["V"].sum() - V) < 1e-12 * V
+    # K_ij = integral grad phi_i . grad phi_j, checked through the Dirichlet energy of random
+    # linear-in-node fields: u^T K u = V |grad u|^2 (exact for P1)
+    Kd = om.K_dense()
+    for _ in range(5):
+        u = rng.standard_normal(4)
+        gu = (u[mesh.tet[0]] [:, None] * g).sum(0)  # noqa: E211
+        assert abs(u @ Kd @ u - V * gu @ gu) < 1e-11 * abs(V * gu @ gu)
+    # charges of a linear magnetisation M(x) = M0 + G x: b_k = integral M . grad phi_k, which the
+    # one-point centroid rule integrates exactly (integrand linear)
+    Dd = om.D_dense()
+    M0 = rng.standard_normal(3); G = rng.standard_normal((3, 3)) * 1e9
+    Mnode = (M0[None, :] + Pm @ G.T)          # [n][3]
+    b = np.einsum("kaj,ja->k", Dd, Mnode)
+    cen = Pm[mesh.tet[0]].mean(0)
+    Mc = M0 + G @ cen
+    kloc = list(mesh.tet[0])
+    for a, k in enumerate(kloc):
+        assert abs(b[k] - V * Mc @ g[a]) < 1e-10 * np.abs(V * Mnode).max() * 1e9
+
+
+def test_cube_linear_field_and_gauss(oracle_mod):
+    xyz, tets = _cube5()
+    mesh = _mesh_from(xyz, tets)
+    om = oracle_mod.OracleMesh(mesh)
+    e = om.export()
+    s = 1e-9
+    assert abs(e["V"].sum() - s ** 3) < 1e-12 * s ** 3
+    Kd = om.K_dense()
+    # K is symmetric positive semidefinite with constants in its null space
+    assert np.allclose(Kd, Kd.T, rtol=0, atol=1e-14 * np.abs(Kd).max())
+    assert np.abs(Kd @ np.ones(8)).max() < 1e-13 * np.abs(Kd).max()
+    assert np.linalg.eigvalsh(Kd).min() > -1e-12 * np.abs(Kd).max()
+    # linear field u = a.x: u^T K u = |a|^2 V exactly
+    a = np.array([0.3, -1.2, 2.0]) / s
+    u = mesh.xyz.T @ a
+    assert abs(u @ Kd @ u - a @ a * s ** 3) < 1e-12 * a @ a * s ** 3
+    # Gauss: uniform m_z has charge only on the top/bottom faces, +/- the lumped face area
+    Dd = om.D_dense()
+    b = Dd[:, 2, :].sum(1)
+    assert abs(b.sum()) < 1e-12 * s * s
+    z = mesh.xyz[2]
+    # face lumped areas for this split: corners of the 2-triangle face (diagonal dependent)
+    top = z > 0.5 * s
+    assert abs(b[top].sum() - s * s) < 1e-12 * s * s
+    assert abs(b[~top].sum() + s * s) < 1e-12 * s * s
+    # uniform m_x: charge only on the x faces
+    bx = Dd[:, 0, :].sum(1)
+    xr = mesh.xyz[0] > 0.5 * s
+    assert abs(bx[xr].sum() - s * s) < 1e-12 * s * s
+
+
+def test_island_mesh_invariants(oracle_mod):
+    mesh, mat, fld = I.single_island_workload()
+    om = oracle_mod.OracleMesh(mesh)
+    e = om.export()
+    P = mesh.xyz.T
+    t = mesh.tet
+    vol = np.einsum("ij,ij->i", P[t[:, 1]] - P[t[:, 0]], np.cross(P[t[:, 2]] - P[t[:, 0]], P[t[:, 3]] - P[t[:, 0]])) / 6
+    assert vol.min() > 0
+    assert abs(e["V"].sum() - vol.sum()) < 1e-12 * vol.sum()
+    # polygonal cylinder volume is close to pi r^2 t
+    assert abs(vol.sum() / (math.pi * 16e-18 * 10e-9) - 1) < 0.03
+    # interface areas sum to the area of the triangulated cross-section
+    assert abs(e["aif"].sum() - vol.sum() / 10e-9) < 1e-9 * e["aif"].sum()
+    Kd = om.K_dense()
+    assert np.abs(Kd @ np.ones(om.n)).max() < 1e-12 * np.abs(Kd).max()
+    # charges: sum over nodes vanishes for any m; interior nodes carry none for uniform m
+    Dd = om.D_dense()
+    m = I.random_unit_m(om.n, 3)
+    b = np.einsum("kaj,aj->k", Dd, m)
+    assert abs(b.sum()) < 1e-12 * np.abs(b).sum()
+    bu = Dd[:, 2, :].sum(1)
+    r = np.hypot(mesh.xyz[0], mesh.xyz[1])
+    z = mesh.xyz[2]
+    iface_nodes = set(mesh.iface.ravel().tolist())
+    interior = (r < 3.0e-9) & (z > 0.5e-9) & (z < 9.5e-9) & np.array([i not in iface_nodes for i in range(om.n)])
+    assert interior.sum() > 10
+    assert np.abs(bu[interior]).max() < 1e-12 * np.abs(bu).max()
+
+
+# ------------------------------------------------------------------------------------------
+# Demag operator
+# ------------------------------------------------------------------------------------------
+
+def _nz_cylinder(a, L):
+    """Magnetometric demag factor of a uniformly magnetised cylinder along its axis, from the
+    Coulomb energy of its two end-face charge disks (pair-distance form, 1-D quadrature)."""
+    def aov(s):
+        return 2 * a * a * math.acos(s / (2 * a)) - 0.5 * s * math.sqrt(4 * a * a - s * s)
+
+    def integral(Lz):
+        f = (lambda s: 2 * math.pi * aov(s) * s / math.hypot(s, Lz)) if Lz > 0 else (lambda s: 2 * math.pi * aov(s))
+        return quad(f, 0, 2 * a, limit=200, epsabs=0, epsrel=1e-12)[0]
+    E_over = (integral(0.0) - integral(L)) / (4 * math.pi)
+    return 2 * E_over / (math.pi * a * a * L)
+
+
+def test_nz_cylinder_reference_limits():
+    # long rod -> 0, flat disk -> 1, and the known value ~0.3116 for height = diameter
+    assert _nz_cylinder(1.0, 200.0) < 0.01
+    tau = 0.005
+    # thin-disk asymptote 1 - (tau/pi)(ln(8/tau) - 1/2), tau = height / radius
+    assert abs(_nz_cylinder(1.0, tau) - (1 - tau / math.pi * (math.log(8 / tau) - 0.5))) < 1e-4
+    assert abs(_nz_cylinder(1.0, 2.0) - 0.3116) < 5e-4
+
+
+def test_demag_S_symmetric_pd_and_entries(oracle_mod):
+    mesh, mat, fld = I.single_island_workload()
+    om = oracle_mod.OracleMesh(mesh)
+    S = om.demag_S()
+    assert np.abs(S - S.T).max() < 1e-14 * np.abs(S).max()
+    np.linalg.cholesky(S)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        k, l = rng.integers(0, om.n, 2)
+        assert abs(om.demag_S_entry(k, l) - S[k, l]) < 1e-12 * abs(S[k, l])
+    # far pairs approach the point-charge kernel 1/(4 pi r) between the phi-weighted centroids
+    e = om.export()
+    P = mesh.xyz.T
+    k = int(np.argmin(P[:, 2] + 10 * np.hypot(P[:, 0], P[:, 1])))
+    l = int(np.argmax(P[:, 2] - 10 * np.hypot(P[:, 0], P[:, 1])))
+    tc = P[mesh.tet].mean(1)
+
+    def charge_centroid(i):
+        sel = np.any(mesh.tet == i, axis=1)
+        w = e["tetV"][sel]
+        return (w[:, None] * tc[sel]).sum(0) / w.sum()
+    r = np.linalg.norm(charge_centroid(k) - charge_centroid(l))
+    assert abs(S[k, l] * 4 * math.pi * r - 1) < 0.01
+
+
+@pytest.mark.slow
+def test_demag_cylinder_convergence(oracle_mod):
+    """Uniform m_z in a cylinder (equal Ms in both layers): the energy-derived demag factor
+    approaches the exact value with an observed order of at least 0.8."""
+    a, ts, th = 4e-9, 3e-9, 7e-9
+    exact = _nz_cylinder(a, ts + th)
+    errs, hs = [], []
+    for h in (1.2e-9, 0.9e-9, 0.7e-9):
+        mesh = I.island_mesh(a, a, ts, th, h, seed=0)
+        om = oracle_mod.OracleMesh(mesh)
+        S = om.demag_S()
+        mat = I.Material(Ms=(1e6, 1e6))
+        m = np.zeros((3, om.n)); m[2] = 1.0
+        _, terms, E = om.fields(S, mat, I.Field(B_peak=0.0), m)
+        V = om.export()["V"]
+        nz = 2 * E[3] / (MU0 * 1e12 * V.sum())
+        # the volume average of B_d equals -mu0 Ms N_z (same number through the field route)
+        bav = (terms[3, 2] * V).sum() / V.sum()
+        assert abs(-bav / (MU0 * 1e6) - nz) < 1e-9
+        errs.append(abs(nz - exact)); hs.append(h)
+    assert errs[0] > errs[1] > errs[2]
+    order = math.log(errs[0] / errs[2]) / math.log(hs[0] / hs[2])
+    assert order >= 0.8
+    assert errs[2] / exact < 0.08
+
+
+# ------------------------------------------------------------------------------------------
+# Field <-> energy consistency (variational definition of every term)
+# ------------------------------------------------------------------------------------------
+
+def test_fields_are_energy_gradients(oracle_mod):
+    mesh = I.island_mesh(3e-9, 3e-9, 2e-9, 3e-9, 1.0e-9, seed=4)
+    om = oracle_mod.OracleMesh(mesh)
+    S = om.demag_S()
+    mat = I.Material(Ms=(0.9e6, 0.55e6), K=(0.3e6, 1.1e6), A=(8e-12, 12e-12),
+                     axis=((0.0, 0.6, 0.8), (0.0, 0.0, 1.0)), A_int=4e-12, alpha=0.1)
+    fld = I.Field(kind=I.FIELD_POLE, B_peak=1.3, dir=(0.3, 0.1, -0.95), t_rise=0.1e-9,
+                  v=(20.0, 0.0, 0.0), x_off=(-2e-9, 1e-9, 0.0), L_grad=5e-9, W_pole=8e-9,
+                  B_ext=(0.01, -0.02, 0.05))
+    m = I.random_unit_m(om.n, 11, cone=1.0)
+    t = 0.05e-9
+    _, terms, E = om.fields(S, mat, fld, m, t=t)
+    V = om.export()["V"]
+    Ms = np.where(mesh.layer == 0, mat.Ms[0], mat.Ms[1])
+    w = Ms * V
+    rng = np.random.default_rng(5)
+    nodes = rng.choice(om.n, 12, replace=False)
+    # include interface nodes explicitly
+    nodes = np.concatenate([nodes, mesh.iface[:3].ravel()])
+    for i in nodes:
+        for c in range(3):
+            eps = 1e-6
+            mp = m.copy(); mp[c, i] += eps
+            mm = m.copy(); mm[c, i] -= eps
+            Ep = om.fields(S, mat, fld, mp, t=t)[2]
+            Em = om.fields(S, mat, fld, mm, t=t)[2]
+            for term in range(5):
+                dE = (Ep[term] - Em[term]) / (2 * eps)
+                B = terms[term, c, i]
+                scale = np.abs(terms[term]).max() + 1e-30
+                assert abs(-dE / w[i] - B) < 2e-6 * scale, (term, i, c)
+
+
+def test_uniform_state_has_no_exchange(oracle_mod):
+    mesh, mat, fld = I.single_island_workload()
+    om = oracle_mod.OracleMesh(mesh)
+    m = np.zeros((3, om.n)); m[0] = 0.6; m[2] = 0.8
+    _, terms, E = om.fields(None, mat, fld, m)
+    mn = I.random_unit_m(om.n, 2, cone=0.5)
+    _, terms2, E2 = om.fields(None, mat, fld, mn)
+    assert abs(E[0]) < 1e-12 * abs(E2[0])
+    assert np.abs(terms[0]).max() < 1e-10 * np.abs(terms2[0]).max()
+    assert E2[0] > 0
+
+
+# ------------------------------------------------------------------------------------------
+# Time integration
+# ------------------------------------------------------------------------------------------
+
+def test_dp5_order_conditions(oracle_mod):
+    c, a, e = oracle_mod.dp5_tableau()
+    b = a[6, :6].tolist() + [0.0]
+    A = np.zeros((7, 7)); A[:, :6] = a
+    # row sums equal the nodes
+    assert np.allclose(A.sum(1), c, atol=1e-15)
+    bb = np.array(b)
+    cc = np.array(c)
+    conds = [(bb.sum(), 1.0), (bb @ cc, 1 / 2), (bb @ cc ** 2, 1 / 3), (bb @ (A @ cc), 1 / 6),
+             (bb @ cc ** 3, 1 / 4), (bb @ (cc * (A @ cc)), 1 / 8), (bb @ (A @ cc ** 2), 1 / 12),
+             (bb @ (A @ (A @ cc)), 1 / 24), (bb @ cc ** 4, 1 / 5)]
+    for lhs, rhs in conds:
+        assert abs(lhs - rhs) < 1e-14
+    # the embedded 4th-order weights bhat = b - e are a valid 4th-order method
+    bh = bb - e
+    for lhs, rhs in [(bh.sum(), 1.0), (bh @ cc, 1 / 2), (bh @ cc ** 2, 1 / 3), (bh @ cc ** 3, 1 / 4),
+                     (bh @ (A @ cc), 1 / 6)]:
+        assert abs(lhs - rhs) < 1e-14
+    # the coefficients are the exact fractions of Dormand & Prince (1980)
+    assert Fraction(a[4, 0]).limit_denominator(10000) == Fraction(19372, 6561)
+    assert Fraction(e[4]).limit_denominator(400000) == Fraction(-17253, 339200)
+
+
+def _macrospin_setup(alpha, B):
+    mesh = I.island_mesh(2e-9, 2e-9, 1e-9, 1e-9, 1.0e-9, seed=0)
+    # no exchange: every node then follows the same macrospin ODE exactly, and large fixed steps
+    # are not limited by the exchange stiffness of the mesh
+    mat = I.Material(K=(0.0, 0.0), A=(0.0, 0.0), A_int=0.0, alpha=alpha)
+    fld = I.Field(kind=I.FIELD_UNIFORM, B_peak=B, dir=(0.0, 0.0, 1.0), t_rise=0.0)
+    return mesh, mat, fld
+
+
+def _macrospin_exact(theta0, alpha, B, t):
+    gp = GAMMA / (1 + alpha * alpha)
+    th = 2 * math.atan(math.tan(theta0 / 2) * math.exp(-alpha * gp * B * t))
+    ph = gp * B * t
+    return np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+
+
+def test_macrospin_closed_form_adaptive(oracle_mod):
+    alpha, B, th0, T = 0.1, 1.0, 2.5, 0.2e-9
+    mesh, mat, fld = _macrospin_setup(alpha, B)
+    om = oracle_mod.OracleMesh(mesh)
+    m0 = np.zeros((3, om.n)); m0[0] = math.sin(th0); m0[2] = math.cos(th0)
+    m, res, _ = om.run(None, [mat], [fld], dict(t_end=T, rtol=1e-10, dt0=1e-15), m0=m0)
+    ex = _macrospin_exact(th0, alpha, B, T)
+    assert res[0]["status"] == 0
+    assert np.abs(m[0] - ex[:, None]).max() < 1e-8
+    # the hard-layer crossing of m_z = 0 happens where theta = pi/2
+    gp = GAMMA / (1 + alpha ** 2)
+    t_cross = math.log(math.tan(th0 / 2)) / (alpha * gp * B)
+    assert abs(res[0]["t_sw"] - t_cross) < 2e-3 * t_cross or not res[0]["switched"]
+
+
+def test_macrospin_fixed_step_order_five(oracle_mod):
+    alpha, B, th0, T = 0.2, 2.0, 2.0, 20e-12
+    mesh, mat, fld = _macrospin_setup(alpha, B)
+    om = oracle_mod.OracleMesh(mesh)
+    m0 = np.zeros((3, om.n)); m0[0] = math.sin(th0); m0[2] = math.cos(th0)
+    ex = _macrospin_exact(th0, alpha, B, T)
+    errs = []
+    dts = [1.0e-12, 0.5e-12, 0.25e-12]
+    for dt in dts:
+        m, res, _ = om.run(None, [mat], [fld], dict(t_end=T, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt), m0=m0)
+        errs.append(np.abs(m[0, :, 0] - ex).max())
+    o1 = math.log2(errs[0] / errs[1]); o2 = math.log2(errs[1] / errs[2])
+    # global order at least five (a wrong coefficient drops it to four or below; the projection
+    # back onto |m| = 1 can only help)
+    assert o1 > 4.5 and o2 > 4.5, (errs, o1, o2)
+
+
+def test_larmor_frequency(oracle_mod):
+    """alpha = 0: free precession at gamma B / (2 pi) = 28.0249514 GHz/T * B."""
+    B = 0.7
+    mesh, mat, fld = _macrospin_setup(0.0, B)
+    om = oracle_mod.OracleMesh(mesh)
+    th0 = 0.4
+    m0 = np.zeros((3, om.n)); m0[0] = math.sin(th0); m0[2] = math.cos(th0)
+    f = 28.0249514e9 * B
+    T = 3.25 / f   # a quarter turn past three full periods
+    m, res, traj = om.run(None, [mat], [fld], dict(t_end=T, rtol=1e-11), m0=m0, traj_cap=200000)
+    phi = math.atan2(m[0, 1, 0], m[0, 0, 0])
+    assert abs(phi - math.pi / 2) < 1e-6
+    assert abs(m[0, 2, 0] - math.cos(th0)) < 1e-9
+
+
+def test_norm_preserved_and_renormalised(oracle_mod):
+    mesh, mat, fld = I.single_island_workload()
+    om = oracle_mod.OracleMesh(mesh)
+    S = om.demag_S()
+    m, res, _ = om.run(S, [mat], [fld], dict(t_end=0.02e-9, rtol=1e-6))
+    nrm = np.sqrt((m[0] ** 2).sum(0))
+    assert np.abs(nrm - 1).max() <= 4 * np.finfo(float).eps
+    assert res[0]["max_norm_dev"] < 50 * 1e-6
+
+
+def test_energy_decays_in_static_field(oracle_mod):
+    mesh = I.island_mesh(3e-9, 3e-9, 2e-9, 3e-9, 1.0e-9, seed=1)
+    om = oracle_mod.OracleMesh(mesh)
+    S = om.demag_S()
+    mat = I.Material(alpha=0.5)
+    fld = I.Field(kind=I.FIELD_UNIFORM, B_peak=1.5, dir=(0.5, 0.0, -math.sqrt(0.75)), t_rise=0.0)
+    m = I.random_unit_m(om.n, 8, cone=0.6)[None]
+    Es = []
+    for _ in range(12):
+        m, res, _ = om.run(S, [mat], [fld], dict(t_end=2e-12, integrator=oracle_mod.DP5_FIXED,
+                                                 dt_fixed=2e-15), m0=m)
+        Es.append(res[0]["energy"])
+    Es = np.array(Es)
+    assert np.all(np.diff(Es) <= 1e-9 * np.abs(Es).max())
+    assert Es[-1] < Es[0]
+
+
+def _sw_field(psi):
+    return (math.cos(psi) ** (2 / 3) + math.sin(psi) ** (2 / 3)) ** -1.5
+
+
+@pytest.mark.parametrize("psi_deg", [10.0, 30.0, 45.0])
+def test_stoner_wohlfarth_astroid(oracle_mod, psi_deg):
+    """Uniform macrospin island (no demag): a static field 3% below the SW field leaves the
+    magnetisation near +z, 3% above reverses it (h(30 deg) = 0.52402 of 2K/Ms)."""
+    psi = math.radians(psi_deg)
+    Ms, K = 0.8e6, 0.5e6
+    BK = 2 * K / Ms
+    mesh = I.island_mesh(2e-9, 2e-9, 1e-9, 1e-9, 1.0e-9, seed=0)
+    om = oracle_mod.OracleMesh(mesh)
+    mat = I.Material(Ms=(Ms, Ms), K=(K, K), A_int=10e-12, alpha=1.0)
+    out = []
+    for fac in (0.97, 1.03):
+        B = fac * _sw_field(psi) * BK
+        fld = I.Field(kind=I.FIELD_UNIFORM, B_peak=B, dir=(math.sin(psi), 0.0, -math.cos(psi)), t_rise=0.0)
+        m, res, _ = om.run(None, [mat], [fld], dict(t_end=1.0e-9, rtol=1e-7))
+        out.append(res[0]["mz_hard"])
+    assert out[0] > 0.0 and out[1] < 0.0, out
+    if psi_deg == 30.0:
+        assert abs(_sw_field(psi) - 0.52402) < 1e-5
+
+
+# ------------------------------------------------------------------------------------------
+# Random numbers
+# ------------------------------------------------------------------------------------------
+
+def test_philox_known_answers(oracle_mod):
+    for row in _golden("philox4x32_10_kat.txt"):
+        v = [int(x, 16) for x in row]
+        out = oracle_mod.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:]
+
+
+def test_gaussians_moments(oracle_mod):
+    g = np.array([oracle_mod.gauss3([7, 9], s, i) for s in range(40) for i in range(250)]).ravel()
+    assert abs(g.mean()) < 0.03 and abs(g.var() - 1) < 0.04
+    assert abs((g ** 4).mean() - 3) < 0.2
+
+
+# ------------------------------------------------------------------------------------------
+# Paper numbers: BER formulas, Table III, media layout
+# ------------------------------------------------------------------------------------------
+
+def test_sigma_example():
+    from oracle import ber
+    row = _golden("media_layout.txt")[1]
+    K, Js, sig = float(row[0]), float(row[1]), float(row[2])
+    s = ber.sigma_T(K, Js)
+    assert round(s, 3) == sig          # the paper's "40 mT"
+    assert abs(s - 0.0403919) < 1e-6     # 0.015 * 2.6928 T
+
+
+def test_table3_sums_and_eq1_eq3():
+    from oracle import ber
+    for row in _golden("table3_ber.txt"):
+        tot, targ, prev, adj = (float(x) for x in row[1:5])
+        K = float(row[6]) * 1e3
+        s = targ + prev + adj
+        # BER_tot is the sum of the three contributions (two significant digits in the paper)
+        assert abs(s - tot) / tot < 0.05
+        # Eq. (1) maps BER back to H_crit and forth without loss
+        sig = ber.sigma_T(K, 0.7)
+        h = ber.h_crit_from_ber(targ, sig)
+        assert abs(ber.ber_crit(h, sig) / targ - 1) < 1e-6   # 1 - erf loses digits in the tail
+        assert 0.5 * sig < h < 8 * sig
+        # Eq. (3): the in-field barrier implied by BER_adj is positive and below E_B0
+        eb = math.log(ber.T_WRITE * ber.F0 / adj)
+        assert 0 < eb < float(row[5])
+
+
+def test_media_layout_density():
+    row = _golden("media_layout.txt")[0]
+    pd, pc, d, dens, fill = (float(x) for x in row)
+    cell_nm2 = pd * pc
+    tb_in2 = (0.0254 / 1e-9) ** 2 / cell_nm2 / 1e12
+    assert round(tb_in2, 2) == dens
+    assert round(math.pi * (d / 2) ** 2 / cell_nm2, 3) == fill
