@@ -1,0 +1,177 @@
+/*
+ * bpm_llg.h -- C ABI of the MI355X batched finite-element LLG island solver and its learned
+ * screen.
+ *
+ * The operation is the recording simulation of Kovacs et al., "Numerical optimization of
+ * writer and media for bit patterned magnetic recording", J. Appl. Phys. 120, 013902 (2016):
+ * the Landau-Lifshitz-Gilbert equation of an exchange-coupled composite island (Sec. II.B,
+ * Fig. 3: soft layer on a hard layer, coupled through an interlayer exchange A_ex,int) driven by
+ * a head field that moves down-track and rises in 0.1 ns plus a global field H_ext (Sec. II.A,
+ * Sec. II.C).  The critical-field search of Sec. II.C (Fig. 4; Eqs. (1)-(2)) runs many such
+ * simulations side by side; here they are instances of one batched launch.
+ *
+ * Conventions
+ *   - SI units; fields are given as B = mu0 H in tesla.
+ *   - Every call returns BPM_OK (0) or a negative status.  On failure bpm_last_error() gives a
+ *     message owned by the context, valid until the next call on that context.
+ *   - Host pointers are caller-owned and only read during the call (copied).  Device pointers
+ *     (marked "device") must stay valid until the work queued on the given stream completes.
+ *   - One context per host thread.  Calls on one context are not thread-safe.
+ *   - A numerical failure of one instance (non-finite state, step underflow, step budget) does
+ *     not fail the run: it is reported in bpm_result.status and the other instances continue.
+ */
+#ifndef BPM_LLG_H
+#define BPM_LLG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BPM_OK = 0,
+  BPM_EINVAL = -1,           /* bad argument (message says which) */
+  BPM_ENOMEM = -2,           /* device or host allocation failed */
+  BPM_EHIP = -3,             /* HIP runtime error */
+  BPM_ESTATE = -4,           /* call out of order (e.g. results before a run) */
+  BPM_ENONFINITE = -5,       /* per instance: magnetisation became non-finite */
+  BPM_ESTEPUNDERFLOW = -6,   /* per instance: adaptive step fell below dt_min */
+  BPM_EMAXSTEPS = -7         /* per instance: max_steps attempts used up */
+};
+
+enum { BPM_FIELD_UNIFORM = 0, BPM_FIELD_POLE = 1 };
+enum { BPM_DP45 = 0, BPM_DP5_FIXED = 1, BPM_HEUN = 2 };
+
+typedef struct bpm_ctx bpm_ctx;
+
+/* Creates a context on HIP device `device`.  *out receives the handle. */
+int bpm_create(bpm_ctx** out, int device);
+void bpm_destroy(bpm_ctx* ctx);
+const char* bpm_last_error(const bpm_ctx* ctx);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Mesh groups                                                                                */
+/* ------------------------------------------------------------------------------------------ */
+/* P1 tetrahedral island mesh.  The paper meshes the island with NETGEN (Sec. II.A); any
+ * conforming mesh is accepted.  Layer 0 is the soft layer (on top, nearest the head), layer 1
+ * the hard layer (Sec. II.B, Fig. 3).  The two layers are meshed separately: nodes on the
+ * interface exist twice, once per layer, and iface lists the pairs (soft node, hard node).   */
+typedef struct {
+  int32_t n_nodes, n_tets, n_iface, pad_;
+  const double* xyz;          /* host [3][n_nodes], metres (SoA) */
+  const int32_t* tet;         /* host [n_tets][4]; orientation free */
+  const int32_t* node_layer;  /* host [n_nodes], 0 soft / 1 hard */
+  const int32_t* iface;       /* host [n_iface][2] (soft node, hard node), may be NULL if 0 */
+} bpm_mesh;
+
+/* Adds a mesh group: assembles the P1 exchange stiffness, charge operator, lumped volumes and
+ * interface areas on the host and copies them to the device.  The dense magnetostatic operator
+ * S (energy (mu0/2) b^T S b of the nodal charges b) is either copied from S_host ([n][n] FP64,
+ * row-major) or, when S_host is NULL, assembled on the GPU from Gaussian charge blobs of
+ * standard deviation demag_beta * V_tet^(1/3) at the tet centroids (demag_beta <= 0 selects the
+ * default 0.29166..., the blob whose self-energy equals a uniformly charged ball).
+ * Errors: BPM_EINVAL for an empty or inconsistent mesh (bad indices, degenerate tets, a node
+ * with no tet, an interface pair not of one soft and one hard node).                         */
+int bpm_mesh_add(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, double demag_beta,
+                 int32_t* mesh_id);
+
+/* Copies the group's FP64 demag operator to host memory S_out [n][n]. */
+int bpm_mesh_get_S(bpm_ctx* ctx, int32_t mesh_id, double* S_out);
+
+/* Copies the host-assembled quantities of a group: V [n], rowptr [n+1], col [nnz], K [nnz],
+ * D [nnz][3] (D_{k,(j,a)} = integral phi_j d_a phi_k for row k, column j), aif [n]; each pointer
+ * may be NULL.  *nnz receives the pattern size. */
+int bpm_mesh_get_assembly(bpm_ctx* ctx, int32_t mesh_id, int32_t* nnz, double* V,
+                          int32_t* rowptr, int32_t* col, double* K, double* D, double* aif);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Instances                                                                                  */
+/* ------------------------------------------------------------------------------------------ */
+/* Per-layer material (index 0 soft, 1 hard): saturation magnetisation Ms (A/m), uniaxial
+ * anisotropy K (J/m^3) along the unit axis, exchange stiffness A (J/m); interlayer exchange
+ * A_int (J/m) across an interlayer of thickness delta_int (m), i.e. a surface coupling
+ * A_int/delta_int (J/m^2) (Sec. II.B, Fig. 3); Gilbert damping alpha.                        */
+typedef struct {
+  double Ms[2], K[2], A[2], axis[2][3];
+  double A_int, delta_int, alpha;
+} bpm_material;
+
+/* Applied field B(x, t) = B_peak r(t) f(x, t) dir + B_ext with the rise r(t) = min(t/t_rise, 1)
+ * (Sec. II.A: the head field is scaled with a 0.1 ns rise; Sec. II.C: a global H_ext).
+ *   BPM_FIELD_UNIFORM: f = 1.
+ *   BPM_FIELD_POLE:    f = fx * fy, a synthetic pole moving with velocity v (Sec. II.A: the
+ *     precomputed head field moves down-track over the bit):
+ *       fx = (1 - tanh(sx / L_grad)) / 2,  sx = x - x_off[0] - v[0] t
+ *       fy = (tanh((sy + W_pole/2)/L_grad) - tanh((sy - W_pole/2)/L_grad)) / 2,
+ *            sy = y - x_off[1] - v[1] t.
+ * Positions x are mesh coordinates plus the instance offset.                                 */
+typedef struct {
+  int32_t kind, pad_;
+  double B_peak, dir[3], t_rise, v[3], x_off[3], L_grad, W_pole, B_ext[3];
+} bpm_field;
+
+/* Adds an instance on mesh group mesh_id.  offset (may be NULL = 0) translates the island;
+ * m0 (host [3][n], may be NULL = +z everywhere) is normalised on upload; seed keys the thermal
+ * noise of BPM_HEUN runs (Philox key = (low 32 bits, high 32 bits)).                          */
+int bpm_instance_add(bpm_ctx* ctx, int32_t mesh_id, const bpm_material* mat,
+                     const bpm_field* field, const double* offset, const double* m0,
+                     uint64_t seed, int32_t* inst_id);
+
+/* Couples instances (all on one mesh group) through far-field point dipoles at the island
+ * centroids: B_J = mu0 sum_{I != J} (3 (mu_I . r^) r^ - mu_I) / (4 pi r^3), mu_I = sum_i Ms V_i
+ * m_i, applied uniformly to island J.  Coupled instances share one clock (one adaptive step). */
+int bpm_couple_dipoles(bpm_ctx* ctx, int32_t n, const int32_t* inst_ids);
+
+/* Removes every instance (mesh groups stay). */
+int bpm_clear_instances(bpm_ctx* ctx);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Runs                                                                                       */
+/* ------------------------------------------------------------------------------------------ */
+/* precision: 32 or 64.  integrator: BPM_DP45 (Dormand-Prince 5(4), error-controlled with the
+ * RMS norm of e / (atol + rtol max(|y_n|,|y_n+1|)), accept at <= 1, next step
+ * dt clamp(0.9 err^-1/5, 0.2, 5), no growth right after a rejection, |m| restored after every
+ * accepted step), BPM_DP5_FIXED (the same stages with dt_fixed, last step clipped to t_end),
+ * BPM_HEUN (stochastic Heun with a Langevin field of variance 2 alpha kB T / (gamma Ms V_i dt)
+ * per component, Philox4x32-10 noise keyed by the instance seed and counter (step, node)).
+ * save_every: trajectory sample every k accepted steps (0 = first and last only); traj_cap:
+ * samples kept per instance.  wg_per_group: workgroups cooperating on one mesh group (0 =
+ * automatic).                                                                                */
+typedef struct {
+  int32_t precision, integrator;
+  double t_end, dt0, dt_fixed, rtol, atol, dt_min, temperature;
+  int64_t max_steps;
+  int32_t save_every, traj_cap;
+  int32_t wg_per_group, pad_;
+} bpm_run_opts;
+
+/* Queues a run of every instance on `hip_stream` (NULL = default stream).  Asynchronous. */
+int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);
+/* Waits for the run; returns the first ABI-level error of the run. */
+int bpm_sync(bpm_ctx* ctx);
+
+/* Per-instance result.  switched: hard-layer <m_z> < 0 at the end (writing succeeded, Sec.
+ * II.C).  t_sw: first time the volume-averaged hard-layer m_z reaches 0 (linear interpolation
+ * between accepted steps; NaN if it never does).  B_sw: |B_applied| at the island centroid at
+ * t_sw.  energy: total energy (J) at t_reached.                                               */
+typedef struct {
+  int32_t status, switched;
+  double t_sw, B_sw, mz_soft, mz_hard, t_reached, energy;
+  int64_t n_accept, n_reject;
+  double dt_min_used, dt_max_used, max_norm_dev;
+} bpm_result;
+
+int bpm_get_results(bpm_ctx* ctx, int32_t n, const int32_t* ids, bpm_result* out);
+/* Trajectory samples [cap][9] = (t, <mx>, <my>, <mz> (moment weighted), <mz>_soft, <mz>_hard
+ * (volume weighted), |B_app(centroid)|, dt, err). */
+int bpm_get_trajectory(bpm_ctx* ctx, int32_t id, double* out, int64_t cap, int64_t* n_written);
+/* Final magnetisation of an instance, host [3][n] FP64. */
+int bpm_get_m(bpm_ctx* ctx, int32_t id, double* m_out);
+/* Wall time of the last run's kernels (ms, HIP events on the run stream) and launch data. */
+int bpm_last_run_info(bpm_ctx* ctx, double* kernel_ms, int32_t* grid, int32_t* wg_per_group);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BPM_LLG_H */

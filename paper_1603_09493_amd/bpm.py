@@ -1,0 +1,247 @@
+"""Thin ctypes binding of libbpmllg.so (include/bpm_llg.h).
+
+Argument marshalling only: every step of the simulation runs in the library's HIP kernels.
+The library must have been built (paper_1603_09493_amd.build_lib); importing this module on a
+machine without it raises immediately -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbpmllg.so")
+
+BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_ESTATE = 0, -1, -2, -3, -4
+BPM_ENONFINITE, BPM_ESTEPUNDERFLOW, BPM_EMAXSTEPS = -5, -6, -7
+FIELD_UNIFORM, FIELD_POLE = 0, 1
+DP45, DP5_FIXED, HEUN = 0, 1, 2
+
+
+class BpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class bpm_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_iface", C.c_int32), ("pad_", C.c_int32),
+                ("xyz", C.c_void_p), ("tet", C.c_void_p), ("node_layer", C.c_void_p), ("iface", C.c_void_p)]
+
+
+class bpm_material(C.Structure):
+    _fields_ = [("Ms", C.c_double * 2), ("K", C.c_double * 2), ("A", C.c_double * 2),
+                ("axis", (C.c_double * 3) * 2), ("A_int", C.c_double), ("delta_int", C.c_double),
+                ("alpha", C.c_double)]
+
+
+class bpm_field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("B_peak", C.c_double), ("dir", C.c_double * 3),
+                ("t_rise", C.c_double), ("v", C.c_double * 3), ("x_off", C.c_double * 3),
+                ("L_grad", C.c_double), ("W_pole", C.c_double), ("B_ext", C.c_double * 3)]
+
+
+class bpm_run_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("integrator", C.c_int32), ("t_end", C.c_double),
+                ("dt0", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
+                ("dt_min", C.c_double), ("temperature", C.c_double), ("max_steps", C.c_int64),
+                ("save_every", C.c_int32), ("traj_cap", C.c_int32), ("wg_per_group", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+class bpm_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("switched", C.c_int32), ("t_sw", C.c_double), ("B_sw", C.c_double),
+                ("mz_soft", C.c_double), ("mz_hard", C.c_double), ("t_reached", C.c_double),
+                ("energy", C.c_double), ("n_accept", C.c_int64), ("n_reject", C.c_int64),
+                ("dt_min_used", C.c_double), ("dt_max_used", C.c_double), ("max_norm_dev", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol declared in include/bpm_llg.h (the load test checks them all)
+SYMBOLS = [
+    "bpm_create", "bpm_destroy", "bpm_last_error", "bpm_mesh_add", "bpm_mesh_get_S",
+    "bpm_mesh_get_assembly", "bpm_instance_add", "bpm_couple_dipoles", "bpm_clear_instances",
+    "bpm_run", "bpm_sync", "bpm_get_results", "bpm_get_trajectory", "bpm_get_m", "bpm_last_run_info",
+]
+
+_lib = None
+
+
+def lib():
+    """Loads libbpmllg.so; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1603_09493_amd.build_lib")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.bpm_create.argtypes = [C.POINTER(P), C.c_int]
+    L.bpm_destroy.argtypes = [P]
+    L.bpm_destroy.restype = None
+    L.bpm_last_error.argtypes = [P]
+    L.bpm_last_error.restype = C.c_char_p
+    L.bpm_mesh_add.argtypes = [P, C.POINTER(bpm_mesh), P, D, C.POINTER(I32)]
+    L.bpm_mesh_get_S.argtypes = [P, I32, P]
+    L.bpm_mesh_get_assembly.argtypes = [P, I32, C.POINTER(I32), P, P, P, P, P, P]
+    L.bpm_instance_add.argtypes = [P, I32, C.POINTER(bpm_material), C.POINTER(bpm_field), P, P, C.c_uint64,
+                                   C.POINTER(I32)]
+    L.bpm_couple_dipoles.argtypes = [P, I32, P]
+    L.bpm_clear_instances.argtypes = [P]
+    L.bpm_run.argtypes = [P, C.POINTER(bpm_run_opts), P]
+    L.bpm_sync.argtypes = [P]
+    L.bpm_get_results.argtypes = [P, I32, P, P]
+    L.bpm_get_trajectory.argtypes = [P, I32, P, I64, C.POINTER(I64)]
+    L.bpm_get_m.argtypes = [P, I32, P]
+    L.bpm_last_run_info.argtypes = [P, C.POINTER(D), C.POINTER(I32), C.POINTER(I32)]
+    for name in SYMBOLS:
+        fn = getattr(L, name)
+        if name not in ("bpm_destroy", "bpm_last_error"):
+            fn.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def material_struct(m) -> bpm_material:
+    s = bpm_material()
+    for i in range(2):
+        s.Ms[i], s.K[i], s.A[i] = m.Ms[i], m.K[i], m.A[i]
+        for c in range(3):
+            s.axis[i][c] = m.axis[i][c]
+    s.A_int, s.delta_int, s.alpha = m.A_int, m.delta_int, m.alpha
+    return s
+
+
+def field_struct(f) -> bpm_field:
+    s = bpm_field()
+    s.kind = f.kind
+    s.B_peak, s.t_rise, s.L_grad, s.W_pole = f.B_peak, f.t_rise, f.L_grad, f.W_pole
+    for c in range(3):
+        s.dir[c], s.v[c], s.x_off[c], s.B_ext[c] = f.dir[c], f.v[c], f.x_off[c], f.B_ext[c]
+    return s
+
+
+class Context:
+    """One bpm_ctx on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.L = lib()
+        self.h = C.c_void_p()
+        rc = self.L.bpm_create(C.byref(self.h), int(device))
+        if rc != 0:
+            raise BpmError(rc, "bpm_create failed (no HIP device?)")
+        self.mesh_n = {}
+
+    def close(self):
+        if self.h:
+            self.L.bpm_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise BpmError(rc, self.L.bpm_last_error(self.h).decode())
+        return rc
+
+    # meshes -------------------------------------------------------------------------------------
+    def mesh_add(self, mesh, S=None, beta=0.0) -> int:
+        xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
+        tet = np.ascontiguousarray(mesh.tet, dtype=np.int32)
+        layer = np.ascontiguousarray(mesh.layer, dtype=np.int32)
+        iface = np.ascontiguousarray(mesh.iface, dtype=np.int32)
+        s = bpm_mesh(int(xyz.shape[1]), int(tet.shape[0]), int(iface.shape[0]), 0, _p(xyz), _p(tet), _p(layer),
+                     _p(iface) if iface.shape[0] else None)
+        Sa = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+        mid = C.c_int32()
+        self._check(self.L.bpm_mesh_add(self.h, C.byref(s), _p(Sa), float(beta), C.byref(mid)))
+        self.mesh_n[mid.value] = int(xyz.shape[1])
+        return mid.value
+
+    def mesh_get_S(self, mid):
+        n = self.mesh_n[mid]
+        S = np.empty((n, n))
+        self._check(self.L.bpm_mesh_get_S(self.h, mid, _p(S)))
+        return S
+
+    def mesh_get_assembly(self, mid):
+        n = self.mesh_n[mid]
+        nnz = C.c_int32()
+        self._check(self.L.bpm_mesh_get_assembly(self.h, mid, C.byref(nnz), None, None, None, None, None, None))
+        V = np.empty(n); rp = np.empty(n + 1, np.int32); col = np.empty(nnz.value, np.int32)
+        K = np.empty(nnz.value); D = np.empty((nnz.value, 3)); aif = np.empty(n)
+        self._check(self.L.bpm_mesh_get_assembly(self.h, mid, C.byref(nnz), _p(V), _p(rp), _p(col), _p(K), _p(D),
+                                                 _p(aif)))
+        return dict(V=V, rowptr=rp, col=col, K=K, D=D, aif=aif)
+
+    # instances ----------------------------------------------------------------------------------
+    def instance_add(self, mid, mat, fld, offset=None, m0=None, seed=0) -> int:
+        ms, fs = material_struct(mat), field_struct(fld)
+        off = None if offset is None else np.ascontiguousarray(offset, dtype=np.float64)
+        m0a = None if m0 is None else np.ascontiguousarray(m0, dtype=np.float64)
+        if m0a is not None and m0a.shape != (3, self.mesh_n[mid]):
+            raise ValueError("m0 must be [3][n]")
+        iid = C.c_int32()
+        self._check(self.L.bpm_instance_add(self.h, mid, C.byref(ms), C.byref(fs), _p(off), _p(m0a),
+                                            C.c_uint64(int(seed)), C.byref(iid)))
+        return iid.value
+
+    def couple_dipoles(self, ids):
+        a = np.ascontiguousarray(ids, dtype=np.int32)
+        self._check(self.L.bpm_couple_dipoles(self.h, len(a), _p(a)))
+
+    def clear_instances(self):
+        self._check(self.L.bpm_clear_instances(self.h))
+
+    # runs ---------------------------------------------------------------------------------------
+    def run(self, t_end, precision=64, integrator=DP45, dt0=1e-15, dt_fixed=0.0, rtol=1e-6, atol=None,
+            dt_min=1e-19, temperature=0.0, max_steps=0, save_every=0, traj_cap=0, wg_per_group=0,
+            stream=None):
+        o = bpm_run_opts()
+        o.precision, o.integrator, o.t_end, o.dt0, o.dt_fixed = precision, integrator, t_end, dt0, dt_fixed
+        o.rtol, o.atol = rtol, (rtol if atol is None else atol)
+        o.dt_min, o.temperature, o.max_steps = dt_min, temperature, max_steps
+        o.save_every, o.traj_cap, o.wg_per_group = save_every, traj_cap, wg_per_group
+        self._check(self.L.bpm_run(self.h, C.byref(o), None if stream is None else C.c_void_p(stream)))
+
+    def sync(self):
+        self._check(self.L.bpm_sync(self.h))
+
+    def results(self, ids):
+        a = np.ascontiguousarray(ids, dtype=np.int32)
+        out = (bpm_result * len(a))()
+        self._check(self.L.bpm_get_results(self.h, len(a), _p(a), out))
+        return [r.as_dict() for r in out]
+
+    def trajectory(self, iid, cap):
+        out = np.zeros((max(cap, 1), 9))
+        nw = C.c_int64()
+        self._check(self.L.bpm_get_trajectory(self.h, iid, _p(out), cap, C.byref(nw)))
+        return out[:nw.value]
+
+    def get_m(self, iid, n):
+        out = np.empty((3, n))
+        self._check(self.L.bpm_get_m(self.h, iid, _p(out)))
+        return out
+
+    def last_run_info(self):
+        ms = C.c_double(); grid = C.c_int32(); G = C.c_int32()
+        self._check(self.L.bpm_last_run_info(self.h, C.byref(ms), C.byref(grid), C.byref(G)))
+        return dict(kernel_ms=ms.value, grid=grid.value, wg_per_group=G.value)
+
+
+def nan_to_none(x):
+    return None if (x is None or (isinstance(x, float) and math.isnan(x))) else x

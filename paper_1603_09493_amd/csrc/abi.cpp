@@ -1,0 +1,677 @@
+// C ABI of the batched FE-LLG island solver: context, mesh groups, instances, runs, results.
+// The declarations and their contracts are in include/bpm_llg.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "bpm_internal.h"
+
+namespace bpm {
+
+std::string hip_err_string(hipError_t e) { return hipGetErrorString(e); }
+
+void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream);
+
+template <typename real>
+hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, int, bool, bool, hipStream_t);
+template <typename real>
+hipError_t max_coresident(int, int, bool, int*, int*);
+template <typename real>
+hipError_t launch_energy(const GroupView<real>*, const int2*, int, const RunParams&, double*, int, int, hipStream_t);
+
+// device copies of the assembled quantities, in one precision
+template <typename real>
+struct DevGeom {
+  int32_t *rowptr = nullptr, *col = nullptr, *layer = nullptr, *partner = nullptr;
+  real *K = nullptr, *D = nullptr, *DT = nullptr, *V = nullptr, *aif = nullptr;
+  double *x = nullptr, *y = nullptr, *z = nullptr;
+};
+
+struct DeviceMesh {
+  DevGeom<double> g64;
+  DevGeom<float> g32;
+};
+
+// one device allocation list, freed together
+struct Arena {
+  std::vector<void*> ptrs;
+  ~Arena() { clear(); }
+  void clear() {
+    for (void* p : ptrs) hipFree(p);
+    ptrs.clear();
+  }
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+};
+
+}  // namespace bpm
+
+using namespace bpm;
+
+struct bpm_ctx {
+  int device = 0;
+  std::string err;
+  hipStream_t own_stream = nullptr;
+  std::vector<std::unique_ptr<MeshGroup>> meshes;
+  std::vector<std::unique_ptr<DeviceMesh>> dmeshes;
+  std::vector<std::unique_ptr<Arena>> mesh_arena;
+  std::vector<Instance> insts;
+  // last run
+  Arena run;
+  hipStream_t run_stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool run_pending = false, have_results = false;
+  int run_precision = 64, run_traj_cap = 0, run_grid = 0, run_G = 0;
+  int run_ninst = 0, run_nsys = 0;
+  std::vector<int32_t> inst_order;         // run slot -> instance id
+  std::vector<int32_t> slot_of;            // instance id -> run slot
+  std::vector<int32_t> slot_group;         // run slot -> mesh id
+  std::vector<int32_t> slot_local;         // run slot -> local index in its group
+  std::vector<int32_t> group_inst0;        // mesh id -> first slot (or -1)
+  std::vector<int32_t> sys_of_slot;
+  SysOut* d_sys_out = nullptr;
+  InstOut* d_inst_out = nullptr;
+  double* d_traj = nullptr;
+  double* d_energy = nullptr;
+  void* d_state_m[2] = {nullptr, nullptr};  // unused placeholder
+  std::vector<void*> group_m;               // per mesh id: device m of the run (precision-typed)
+  std::vector<SysOut> h_sys_out;
+  std::vector<InstOut> h_inst_out;
+  std::vector<double> h_energy;
+  float kernel_ms = 0.f;
+};
+
+static int fail(bpm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                            \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess) return fail(ctx, BPM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+extern "C" {
+
+int bpm_create(bpm_ctx** out, int device) {
+  if (!out) return BPM_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BPM_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return BPM_EHIP;
+  bpm_ctx* c = new bpm_ctx();
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return BPM_EHIP;
+  }
+  *out = c;
+  return BPM_OK;
+}
+
+void bpm_destroy(bpm_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->run_pending && c->run_stream) hipStreamSynchronize(c->run_stream);
+  c->run.clear();
+  for (auto& m : c->meshes) {
+    if (m->dS64) hipFree(m->dS64);
+    if (m->dS32) hipFree(m->dS32);
+  }
+  c->mesh_arena.clear();
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+const char* bpm_last_error(const bpm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+template <typename real>
+static int upload_geom(bpm_ctx* c, const MeshGroup& g, DevGeom<real>& d, Arena& A) {
+  std::vector<real> K(g.K.begin(), g.K.end()), D(g.D.begin(), g.D.end()), DT(g.DT.begin(), g.DT.end());
+  std::vector<real> V(g.V.begin(), g.V.end()), aif(g.aif.begin(), g.aif.end());
+  HIPCHK(c, A.alloc(&d.rowptr, g.n + 1));
+  HIPCHK(c, A.alloc(&d.col, g.nnz));
+  HIPCHK(c, A.alloc(&d.layer, g.n));
+  HIPCHK(c, A.alloc(&d.partner, g.n));
+  HIPCHK(c, A.alloc(&d.K, g.nnz));
+  HIPCHK(c, A.alloc(&d.D, 3 * (size_t)g.nnz));
+  HIPCHK(c, A.alloc(&d.DT, 3 * (size_t)g.nnz));
+  HIPCHK(c, A.alloc(&d.V, g.n));
+  HIPCHK(c, A.alloc(&d.aif, g.n));
+  HIPCHK(c, A.alloc(&d.x, g.n));
+  HIPCHK(c, A.alloc(&d.y, g.n));
+  HIPCHK(c, A.alloc(&d.z, g.n));
+  HIPCHK(c, hipMemcpy(d.rowptr, g.rowptr.data(), sizeof(int32_t) * (g.n + 1), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.col, g.col.data(), sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.layer, g.layer.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.partner, g.partner.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.K, K.data(), sizeof(real) * g.nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.D, D.data(), sizeof(real) * 3 * g.nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.DT, DT.data(), sizeof(real) * 3 * g.nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.V, V.data(), sizeof(real) * g.n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.aif, aif.data(), sizeof(real) * g.n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.x, g.x.data(), sizeof(double) * g.n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.y, g.y.data(), sizeof(double) * g.n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.z, g.z.data(), sizeof(double) * g.n, hipMemcpyHostToDevice));
+  return BPM_OK;
+}
+
+extern "C" {
+
+int bpm_mesh_add(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double demag_beta, int32_t* mesh_id) {
+  if (!c) return BPM_EINVAL;
+  if (!mesh || !mesh_id || !mesh->xyz || !mesh->tet || !mesh->node_layer)
+    return fail(c, BPM_EINVAL, "bpm_mesh_add: null argument");
+  if (mesh->n_nodes <= 0 || mesh->n_tets <= 0 || mesh->n_iface < 0 || (mesh->n_iface > 0 && !mesh->iface))
+    return fail(c, BPM_EINVAL, "bpm_mesh_add: empty mesh or bad sizes");
+  if (mesh->n_nodes > 65535) return fail(c, BPM_EINVAL, "bpm_mesh_add: more than 65535 nodes per island");
+  hipSetDevice(c->device);
+  auto g = std::make_unique<MeshGroup>();
+  const int n = mesh->n_nodes;
+  g->n = n;
+  g->ntet = mesh->n_tets;
+  g->nif = mesh->n_iface;
+  g->x.assign(mesh->xyz, mesh->xyz + n);
+  g->y.assign(mesh->xyz + n, mesh->xyz + 2 * n);
+  g->z.assign(mesh->xyz + 2 * n, mesh->xyz + 3 * n);
+  g->tet.assign(mesh->tet, mesh->tet + 4 * (size_t)mesh->n_tets);
+  for (int32_t v : g->tet)
+    if (v < 0 || v >= n) return fail(c, BPM_EINVAL, "bpm_mesh_add: tet index out of range");
+  g->layer.assign(mesh->node_layer, mesh->node_layer + n);
+  for (int32_t v : g->layer)
+    if (v != 0 && v != 1) return fail(c, BPM_EINVAL, "bpm_mesh_add: node_layer must be 0 or 1");
+  if (g->nif) g->iface.assign(mesh->iface, mesh->iface + 2 * (size_t)g->nif);
+  std::string err;
+  int rc = assemble_mesh(*g, err);
+  if (rc) return fail(c, rc, "bpm_mesh_add: " + err);
+  auto dm = std::make_unique<DeviceMesh>();
+  auto arena = std::make_unique<Arena>();
+  if ((rc = upload_geom<double>(c, *g, dm->g64, *arena))) return rc;
+  if ((rc = upload_geom<float>(c, *g, dm->g32, *arena))) return rc;
+  const int ldS = (n + 15) / 16 * 16;
+  if (S_host) {
+    HIPCHK(c, hipMalloc(&g->dS64, sizeof(double) * (size_t)n * ldS));
+    HIPCHK(c, hipMemset(g->dS64, 0, sizeof(double) * (size_t)n * ldS));
+    HIPCHK(c, hipMemcpy2D(g->dS64, sizeof(double) * ldS, S_host, sizeof(double) * n, sizeof(double) * n, n,
+                          hipMemcpyHostToDevice));
+  } else {
+    double beta = demag_beta > 0.0 ? demag_beta : 5.0 / (6.0 * std::sqrt(kPi)) * std::cbrt(3.0 / (4.0 * kPi));
+    rc = demag_assemble_device(*g, beta, c->own_stream, err);
+    if (rc) return fail(c, rc, "bpm_mesh_add: " + err);
+  }
+  HIPCHK(c, hipMalloc(&g->dS32, sizeof(float) * (size_t)n * ldS));
+  to_float_device((size_t)n * ldS, g->dS64, g->dS32, c->own_stream);
+  HIPCHK(c, hipStreamSynchronize(c->own_stream));
+  g->S_ready = true;
+  *mesh_id = (int32_t)c->meshes.size();
+  c->meshes.push_back(std::move(g));
+  c->dmeshes.push_back(std::move(dm));
+  c->mesh_arena.push_back(std::move(arena));
+  return BPM_OK;
+}
+
+int bpm_mesh_get_S(bpm_ctx* c, int32_t id, double* S_out) {
+  if (!c || !S_out || id < 0 || id >= (int)c->meshes.size()) return fail(c, BPM_EINVAL, "bpm_mesh_get_S: bad argument");
+  hipSetDevice(c->device);
+  const MeshGroup& g = *c->meshes[id];
+  const int ldS = (g.n + 15) / 16 * 16;
+  HIPCHK(c, hipMemcpy2D(S_out, sizeof(double) * g.n, g.dS64, sizeof(double) * ldS, sizeof(double) * g.n, g.n,
+                        hipMemcpyDeviceToHost));
+  return BPM_OK;
+}
+
+int bpm_mesh_get_assembly(bpm_ctx* c, int32_t id, int32_t* nnz, double* V, int32_t* rowptr, int32_t* col,
+                          double* K, double* D, double* aif) {
+  if (!c || id < 0 || id >= (int)c->meshes.size()) return fail(c, BPM_EINVAL, "bpm_mesh_get_assembly: bad mesh id");
+  const MeshGroup& g = *c->meshes[id];
+  if (nnz) *nnz = g.nnz;
+  if (V) std::copy(g.V.begin(), g.V.end(), V);
+  if (rowptr) std::copy(g.rowptr.begin(), g.rowptr.end(), rowptr);
+  if (col) std::copy(g.col.begin(), g.col.end(), col);
+  if (K) std::copy(g.K.begin(), g.K.end(), K);
+  if (D) std::copy(g.D.begin(), g.D.end(), D);
+  if (aif) std::copy(g.aif.begin(), g.aif.end(), aif);
+  return BPM_OK;
+}
+
+int bpm_instance_add(bpm_ctx* c, int32_t mesh_id, const bpm_material* mat, const bpm_field* f,
+                     const double* offset, const double* m0, uint64_t seed, int32_t* inst_id) {
+  if (!c) return BPM_EINVAL;
+  if (!mat || !f || !inst_id) return fail(c, BPM_EINVAL, "bpm_instance_add: null argument");
+  if (mesh_id < 0 || mesh_id >= (int)c->meshes.size()) return fail(c, BPM_EINVAL, "bpm_instance_add: bad mesh id");
+  if (f->kind != BPM_FIELD_UNIFORM && f->kind != BPM_FIELD_POLE) return fail(c, BPM_EINVAL, "bpm_instance_add: bad field kind");
+  for (int L = 0; L < 2; ++L)
+    if (!(mat->Ms[L] > 0.0)) return fail(c, BPM_EINVAL, "bpm_instance_add: Ms must be positive");
+  if (!(mat->delta_int > 0.0) || !(mat->alpha >= 0.0)) return fail(c, BPM_EINVAL, "bpm_instance_add: delta_int > 0 and alpha >= 0 required");
+  if (f->kind == BPM_FIELD_POLE && !(f->L_grad > 0.0)) return fail(c, BPM_EINVAL, "bpm_instance_add: L_grad must be positive");
+  const MeshGroup& g = *c->meshes[mesh_id];
+  Instance I;
+  I.mesh = mesh_id;
+  InstConst& k = I.c;
+  for (int L = 0; L < 2; ++L) {
+    k.Ms[L] = mat->Ms[L];
+    k.cex[L] = 2.0 * mat->A[L] / mat->Ms[L];
+    k.can[L] = 2.0 * mat->K[L] / mat->Ms[L];
+    double nrm = std::sqrt(mat->axis[L][0] * mat->axis[L][0] + mat->axis[L][1] * mat->axis[L][1] + mat->axis[L][2] * mat->axis[L][2]);
+    if (!(nrm > 0.0)) return fail(c, BPM_EINVAL, "bpm_instance_add: zero anisotropy axis");
+    for (int d = 0; d < 3; ++d) k.axis[L][d] = mat->axis[L][d] / nrm;
+    k.cint[L] = mat->A_int / mat->delta_int / mat->Ms[L];
+    k.A[L] = mat->A[L];
+    k.K[L] = mat->K[L];
+  }
+  k.Jint = mat->A_int / mat->delta_int;
+  k.alpha = mat->alpha;
+  k.gp = kGammaE / (1.0 + mat->alpha * mat->alpha);
+  k.fkind = f->kind;
+  k.B_peak = f->B_peak;
+  k.t_rise = f->t_rise;
+  k.L_grad = f->L_grad;
+  k.W_pole = f->W_pole;
+  for (int d = 0; d < 3; ++d) {
+    k.dir[d] = f->dir[d];
+    k.v[d] = f->v[d];
+    k.x_off[d] = f->x_off[d];
+    k.B_ext[d] = f->B_ext[d];
+    k.off[d] = offset ? offset[d] : 0.0;
+  }
+  k.key[0] = (uint32_t)seed;
+  k.key[1] = (uint32_t)(seed >> 32);
+  I.m0.resize(3 * (size_t)g.n);
+  for (int i = 0; i < g.n; ++i) {
+    double a = m0 ? m0[i] : 0.0, b = m0 ? m0[g.n + i] : 0.0, d = m0 ? m0[2 * g.n + i] : 1.0;
+    double l = std::sqrt(a * a + b * b + d * d);
+    if (!(l > 0.0) || !std::isfinite(l)) {
+      // a non-finite or zero initial vector is kept as is: the run reports BPM_ENONFINITE
+      l = 1.0;
+    }
+    I.m0[i] = a / l;
+    I.m0[g.n + i] = b / l;
+    I.m0[2 * g.n + i] = d / l;
+  }
+  *inst_id = (int32_t)c->insts.size();
+  c->insts.push_back(std::move(I));
+  c->have_results = false;
+  return BPM_OK;
+}
+
+int bpm_couple_dipoles(bpm_ctx* c, int32_t n, const int32_t* ids) {
+  if (!c) return BPM_EINVAL;
+  if (n < 2 || !ids) return fail(c, BPM_EINVAL, "bpm_couple_dipoles: need at least two instances");
+  if (n > kMaxInstPerGroup) return fail(c, BPM_EINVAL, "bpm_couple_dipoles: too many instances");
+  int mesh = -1;
+  for (int i = 0; i < n; ++i) {
+    if (ids[i] < 0 || ids[i] >= (int)c->insts.size()) return fail(c, BPM_EINVAL, "bpm_couple_dipoles: bad instance id");
+    if (c->insts[ids[i]].coupled) return fail(c, BPM_EINVAL, "bpm_couple_dipoles: instance already coupled");
+    if (mesh < 0) mesh = c->insts[ids[i]].mesh;
+    if (c->insts[ids[i]].mesh != mesh) return fail(c, BPM_EINVAL, "bpm_couple_dipoles: instances on different meshes");
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double* a = c->insts[ids[i]].c.off;
+      const double* b = c->insts[ids[j]].c.off;
+      if (a[0] == b[0] && a[1] == b[1] && a[2] == b[2]) return fail(c, BPM_EINVAL, "bpm_couple_dipoles: two islands at one position");
+    }
+  for (int i = 0; i < n; ++i) {
+    c->insts[ids[i]].coupled = true;
+    c->insts[ids[i]].sys = ids[0];
+  }
+  c->have_results = false;
+  return BPM_OK;
+}
+
+int bpm_clear_instances(bpm_ctx* c) {
+  if (!c) return BPM_EINVAL;
+  if (c->run_pending) return fail(c, BPM_ESTATE, "bpm_clear_instances: a run is pending; call bpm_sync first");
+  c->insts.clear();
+  c->have_results = false;
+  return BPM_OK;
+}
+
+}  // extern "C"
+
+template <typename real>
+static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
+  Arena& A = c->run;
+  A.clear();
+  const int nm = (int)c->meshes.size();
+  // order instances by mesh group, coupled sets contiguous (system root order)
+  std::vector<std::vector<int32_t>> by_mesh(nm);
+  for (int32_t i = 0; i < (int32_t)c->insts.size(); ++i) by_mesh[c->insts[i].mesh].push_back(i);
+  c->inst_order.clear();
+  c->slot_of.assign(c->insts.size(), -1);
+  c->slot_group.clear();
+  c->slot_local.clear();
+  c->group_inst0.assign(nm, -1);
+  std::vector<int32_t> group_ids;
+  std::vector<SysView> sysv;
+  std::vector<InstConst> ic;
+  std::vector<int32_t> group_sys0, group_nsys;
+  for (int mi = 0; mi < nm; ++mi) {
+    auto& v = by_mesh[mi];
+    if (v.empty()) continue;
+    std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+      int ra = c->insts[a].coupled ? c->insts[a].sys : a, rb = c->insts[b].coupled ? c->insts[b].sys : b;
+      return ra < rb;
+    });
+    if ((int)v.size() > kMaxInstPerGroup)
+      return fail(c, BPM_EINVAL, "bpm_run: more than 64 instances on one mesh group");
+    group_ids.push_back(mi);
+    c->group_inst0[mi] = (int32_t)c->inst_order.size();
+    group_sys0.push_back((int32_t)sysv.size());
+    int local = 0;
+    int last_root = -1;
+    for (int32_t id : v) {
+      const int root = c->insts[id].coupled ? c->insts[id].sys : id;
+      if (root != last_root) {
+        SysView sv{(int32_t)c->inst_order.size(), 0, c->insts[id].coupled ? 1 : 0, 0};
+        sysv.push_back(sv);
+        last_root = root;
+      }
+      sysv.back().count++;
+      c->slot_of[id] = (int32_t)c->inst_order.size();
+      c->inst_order.push_back(id);
+      c->slot_group.push_back(mi);
+      c->slot_local.push_back(local++);
+      InstConst k = c->insts[id].c;
+      k.group = (int32_t)group_ids.size() - 1;
+      k.sys = (int32_t)sysv.size() - 1;
+      k.local = local - 1;
+      ic.push_back(k);
+    }
+    group_nsys.push_back((int32_t)sysv.size() - group_sys0.back());
+  }
+  const int ng = (int)group_ids.size();
+  const int ninst = (int)ic.size(), nsys = (int)sysv.size();
+  c->sys_of_slot.resize(ninst);
+  for (int s = 0; s < ninst; ++s) c->sys_of_slot[s] = ic[s].sys;
+  if (ng == 0) return fail(c, BPM_ESTATE, "bpm_run: no instances");
+
+  // launch shape
+  const bool fixed = o->integrator == BPM_DP5_FIXED;
+  int ldS_max = 16, Rmax = 1, nmax = 1;
+  for (int gi = 0; gi < ng; ++gi) {
+    const MeshGroup& g = *c->meshes[group_ids[gi]];
+    ldS_max = std::max(ldS_max, (g.n + 15) / 16 * 16);
+    nmax = std::max(nmax, g.n);
+    Rmax = std::max(Rmax, (int)by_mesh[group_ids[gi]].size());
+  }
+  const size_t lds_budget = 96 * 1024;
+  int RB = (int)std::max<size_t>(1, std::min<size_t>(16, lds_budget / (sizeof(real) * (size_t)ldS_max)));
+  RB = std::min(RB, Rmax);
+  if ((size_t)RB * ldS_max * sizeof(real) > 120 * 1024)
+    return fail(c, BPM_EINVAL, "bpm_run: island too large for the LDS staging of the demag product");
+  int per_cu = 0, cus = 0;
+  {
+    hipError_t e = max_coresident<real>(RB, ldS_max, fixed, &per_cu, &cus);
+    if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+  }
+  const int cap = std::max(1, per_cu * cus);
+  std::vector<int> G(ng, 1);
+  bool coop = false;
+  if (o->wg_per_group > 0) {
+    for (int gi = 0; gi < ng; ++gi) G[gi] = std::max(1, std::min(o->wg_per_group, c->meshes[group_ids[gi]]->n / 8));
+  } else if (ng < cap) {
+    // share the resident workgroups among the groups in proportion to their demag work
+    std::vector<double> w(ng);
+    double tot = 0.0;
+    for (int gi = 0; gi < ng; ++gi) {
+      const MeshGroup& g = *c->meshes[group_ids[gi]];
+      w[gi] = (double)g.n * g.n * by_mesh[group_ids[gi]].size();
+      tot += w[gi];
+    }
+    for (int gi = 0; gi < ng; ++gi) {
+      const int nmaxwg = std::max(1, c->meshes[group_ids[gi]]->n / 16);
+      G[gi] = std::max(1, std::min(nmaxwg, (int)std::floor(cap * 0.5 * w[gi] / tot)));
+    }
+  }
+  int grid = 0;
+  for (int gi = 0; gi < ng; ++gi) {
+    grid += G[gi];
+    if (G[gi] > 1) coop = true;
+  }
+  if (coop && grid > cap) return fail(c, BPM_EINVAL, "bpm_run: workgroups per group exceed the resident capacity");
+  c->run_grid = grid;
+  c->run_G = *std::max_element(G.begin(), G.end());
+
+  // device buffers
+  InstConst* d_ic;
+  SysView* d_sys;
+  int2* d_map;
+  int2* d_imap;
+  double *d_err, *d_obs, *d_mom;
+  unsigned long long* d_bar;
+  GroupView<real>* d_groups;
+  HIPCHK(c, A.alloc(&d_ic, ninst));
+  HIPCHK(c, A.alloc(&d_sys, nsys));
+  HIPCHK(c, A.alloc(&d_map, grid));
+  HIPCHK(c, A.alloc(&d_imap, ninst));
+  HIPCHK(c, A.alloc(&d_err, (size_t)nsys * 3));
+  HIPCHK(c, A.alloc(&d_obs, (size_t)ninst * 3 * 6));
+  HIPCHK(c, A.alloc(&d_mom, (size_t)ninst * 3 * 3));
+  HIPCHK(c, A.alloc(&d_bar, ng));
+  HIPCHK(c, A.alloc(&d_groups, ng));
+  HIPCHK(c, A.alloc(&c->d_sys_out, nsys));
+  HIPCHK(c, A.alloc(&c->d_inst_out, ninst));
+  HIPCHK(c, A.alloc(&c->d_energy, ninst));
+  const int tcap = std::max(0, o->traj_cap);
+  HIPCHK(c, A.alloc(&c->d_traj, (size_t)ninst * std::max(1, tcap) * kTrajW));
+
+  std::vector<GroupView<real>> gv(ng);
+  std::vector<int2> wmap;
+  std::vector<int2> imap(ninst);
+  c->group_m.assign(nm, nullptr);
+  int wg = 0;
+  for (int gi = 0; gi < ng; ++gi) {
+    const int mi = group_ids[gi];
+    const MeshGroup& g = *c->meshes[mi];
+    const DevGeom<real>& d = std::is_same<real, double>::value
+                                 ? *reinterpret_cast<const DevGeom<real>*>(&c->dmeshes[mi]->g64)
+                                 : *reinterpret_cast<const DevGeom<real>*>(&c->dmeshes[mi]->g32);
+    GroupView<real>& v = gv[gi];
+    const int R = (int)by_mesh[mi].size();
+    v.n = g.n; v.nnz = g.nnz; v.R = R; v.nsys = group_nsys[gi];
+    v.ldS = (g.n + 15) / 16 * 16;
+    v.wg0 = wg; v.G = G[gi];
+    v.inst0 = c->group_inst0[mi]; v.sys0 = group_sys0[gi];
+    v.rowptr = d.rowptr; v.col = d.col; v.K = d.K; v.D = d.D; v.DT = d.DT;
+    v.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
+    v.V = d.V; v.layer = d.layer; v.partner = d.partner; v.aif = d.aif;
+    v.x = d.x; v.y = d.y; v.z = d.z;
+    for (int k = 0; k < 3; ++k) v.cen[k] = g.centroid[k];
+    v.Vsoft = g.vol_layer[0]; v.Vhard = g.vol_layer[1];
+    const size_t st3 = (size_t)3 * g.n;
+    HIPCHK(c, A.alloc(&v.m, R * st3));
+    HIPCHK(c, A.alloc(&v.ys, 2 * R * st3));
+    HIPCHK(c, A.alloc(&v.k, 7 * R * st3));
+    HIPCHK(c, A.alloc(&v.yex, R * st3));
+    HIPCHK(c, A.alloc(&v.b, (size_t)R * g.n));
+    HIPCHK(c, A.alloc(&v.u, (size_t)R * g.n));
+    HIPCHK(c, hipMemsetAsync(v.k, 0, sizeof(real) * 7 * R * st3, stream));
+    v.bar = d_bar + gi;
+    c->group_m[mi] = v.m;
+    std::vector<real> m0(R * st3);
+    for (int r = 0; r < R; ++r) {
+      const auto& src = c->insts[by_mesh[mi][r]].m0;
+      for (size_t q = 0; q < st3; ++q) m0[r * st3 + q] = (real)src[q];
+      imap[v.inst0 + r] = make_int2(gi, r);
+    }
+    HIPCHK(c, hipMemcpyAsync(v.m, m0.data(), sizeof(real) * m0.size(), hipMemcpyHostToDevice, stream));
+    for (int w = 0; w < G[gi]; ++w) wmap.push_back(make_int2(gi, w));
+    wg += G[gi];
+  }
+  HIPCHK(c, hipMemcpyAsync(d_groups, gv.data(), sizeof(GroupView<real>) * ng, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_ic, ic.data(), sizeof(InstConst) * ninst, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_sys, sysv.data(), sizeof(SysView) * nsys, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_map, wmap.data(), sizeof(int2) * grid, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_imap, imap.data(), sizeof(int2) * ninst, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemsetAsync(d_err, 0, sizeof(double) * nsys * 3, stream));
+  HIPCHK(c, hipMemsetAsync(d_obs, 0, sizeof(double) * ninst * 18, stream));
+  HIPCHK(c, hipMemsetAsync(d_mom, 0, sizeof(double) * ninst * 9, stream));
+  HIPCHK(c, hipMemsetAsync(d_bar, 0, sizeof(unsigned long long) * ng, stream));
+  HIPCHK(c, hipMemsetAsync(c->d_sys_out, 0, sizeof(SysOut) * nsys, stream));
+  HIPCHK(c, hipMemsetAsync(c->d_inst_out, 0, sizeof(InstOut) * ninst, stream));
+
+  RunParams P{};
+  P.ngroups = ng; P.ninst = ninst; P.nsys = nsys; P.integrator = o->integrator;
+  P.t_end = o->t_end; P.dt0 = o->dt0; P.dt_fixed = o->dt_fixed; P.rtol = o->rtol; P.atol = o->atol;
+  P.dt_min = o->dt_min; P.temperature = o->temperature; P.max_steps = o->max_steps;
+  P.save_every = o->save_every; P.traj_cap = tcap;
+  P.inst = d_ic; P.sys = d_sys; P.sys_out = c->d_sys_out; P.inst_out = c->d_inst_out; P.traj = c->d_traj;
+  P.err_acc = d_err; P.obs_acc = d_obs; P.mom_acc = d_mom; P.wg_map = d_map;
+
+  HIPCHK(c, hipEventRecord(c->ev0, stream));
+  {
+    hipError_t e = launch_dp5<real>(d_groups, P, grid, RB, ldS_max, fixed, coop, stream);
+    if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("stepping kernel launch: ") + hipGetErrorString(e));
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, stream));
+  {
+    hipError_t e = launch_energy<real>(d_groups, d_imap, ninst, P, c->d_energy, ldS_max, nmax, stream);
+    if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("energy kernel launch: ") + hipGetErrorString(e));
+  }
+  c->run_ninst = ninst;
+  c->run_nsys = nsys;
+  c->run_traj_cap = tcap;
+  c->run_precision = sizeof(real) == 8 ? 64 : 32;
+  c->run_stream = stream;
+  c->run_pending = true;
+  c->have_results = false;
+  return BPM_OK;
+}
+
+extern "C" {
+
+int bpm_run(bpm_ctx* c, const bpm_run_opts* o, void* hip_stream) {
+  if (!c) return BPM_EINVAL;
+  if (!o) return fail(c, BPM_EINVAL, "bpm_run: null options");
+  if (c->run_pending) return fail(c, BPM_ESTATE, "bpm_run: previous run not synchronised");
+  if (o->precision != 32 && o->precision != 64) return fail(c, BPM_EINVAL, "bpm_run: precision must be 32 or 64");
+  if (o->integrator != BPM_DP45 && o->integrator != BPM_DP5_FIXED)
+    return fail(c, BPM_EINVAL, "bpm_run: integrator not supported by this entry point");
+  if (!(o->t_end >= 0.0) || !std::isfinite(o->t_end)) return fail(c, BPM_EINVAL, "bpm_run: t_end must be finite and >= 0");
+  if (o->integrator == BPM_DP5_FIXED && !(o->dt_fixed > 0.0)) return fail(c, BPM_EINVAL, "bpm_run: dt_fixed must be > 0");
+  if (o->integrator == BPM_DP45 && (!(o->dt0 > 0.0) || !(o->rtol > 0.0) || !(o->atol > 0.0)))
+    return fail(c, BPM_EINVAL, "bpm_run: dt0, rtol, atol must be > 0");
+  if (o->traj_cap < 0) return fail(c, BPM_EINVAL, "bpm_run: traj_cap must be >= 0");
+  if (c->insts.empty()) return fail(c, BPM_ESTATE, "bpm_run: no instances");
+  hipSetDevice(c->device);
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->own_stream;
+  return o->precision == 64 ? run_typed<double>(c, o, s) : run_typed<float>(c, o, s);
+}
+
+int bpm_sync(bpm_ctx* c) {
+  if (!c) return BPM_EINVAL;
+  if (!c->run_pending) return c->have_results ? BPM_OK : fail(c, BPM_ESTATE, "bpm_sync: no run queued");
+  hipSetDevice(c->device);
+  c->run_pending = false;
+  HIPCHK(c, hipStreamSynchronize(c->run_stream));
+  HIPCHK(c, hipEventElapsedTime(&c->kernel_ms, c->ev0, c->ev1));
+  c->h_sys_out.resize(c->run_nsys);
+  c->h_inst_out.resize(c->run_ninst);
+  c->h_energy.resize(c->run_ninst);
+  HIPCHK(c, hipMemcpy(c->h_sys_out.data(), c->d_sys_out, sizeof(SysOut) * c->run_nsys, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(c->h_inst_out.data(), c->d_inst_out, sizeof(InstOut) * c->run_ninst, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(c->h_energy.data(), c->d_energy, sizeof(double) * c->run_ninst, hipMemcpyDeviceToHost));
+  c->have_results = true;
+  return BPM_OK;
+}
+
+static double applied_mag(const InstConst& k, const MeshGroup& g, double t) {
+  double amp = k.B_peak * (k.t_rise > 0.0 ? std::min(t / k.t_rise, 1.0) : 1.0);
+  if (k.fkind == BPM_FIELD_POLE) {
+    const double sx = g.centroid[0] + k.off[0] - k.x_off[0] - k.v[0] * t;
+    const double sy = g.centroid[1] + k.off[1] - k.x_off[1] - k.v[1] * t;
+    amp *= 0.5 * (1.0 - std::tanh(sx / k.L_grad)) * 0.5 *
+           (std::tanh((sy + 0.5 * k.W_pole) / k.L_grad) - std::tanh((sy - 0.5 * k.W_pole) / k.L_grad));
+  }
+  double b[3];
+  for (int d = 0; d < 3; ++d) b[d] = amp * k.dir[d] + k.B_ext[d];
+  return std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+}
+
+int bpm_get_results(bpm_ctx* c, int32_t n, const int32_t* ids, bpm_result* out) {
+  if (!c) return BPM_EINVAL;
+  if (n < 0 || (n > 0 && (!ids || !out))) return fail(c, BPM_EINVAL, "bpm_get_results: bad argument");
+  if (!c->have_results) return fail(c, BPM_ESTATE, "bpm_get_results: no synchronised run");
+  for (int q = 0; q < n; ++q) {
+    const int id = ids[q];
+    if (id < 0 || id >= (int)c->slot_of.size() || c->slot_of[id] < 0) return fail(c, BPM_EINVAL, "bpm_get_results: bad instance id");
+    const int s = c->slot_of[id];
+    const SysOut& so = c->h_sys_out[c->sys_of_slot[s]];
+    const InstOut& io = c->h_inst_out[s];
+    bpm_result& r = out[q];
+    r.status = so.status;
+    r.switched = io.switched;
+    r.t_sw = io.crossed ? io.t_sw : NAN;
+    r.B_sw = io.crossed ? applied_mag(c->insts[id].c, *c->meshes[c->insts[id].mesh], io.t_sw) : NAN;
+    r.mz_soft = io.mz_soft;
+    r.mz_hard = io.mz_hard;
+    r.t_reached = so.t_reached;
+    r.energy = c->h_energy[s];
+    r.n_accept = so.n_accept;
+    r.n_reject = so.n_reject;
+    r.dt_min_used = so.dt_min_used;
+    r.dt_max_used = so.dt_max_used;
+    r.max_norm_dev = so.max_norm_dev;
+  }
+  return BPM_OK;
+}
+
+int bpm_get_trajectory(bpm_ctx* c, int32_t id, double* out, int64_t cap, int64_t* n_written) {
+  if (!c) return BPM_EINVAL;
+  if (!out || !n_written || cap < 0) return fail(c, BPM_EINVAL, "bpm_get_trajectory: bad argument");
+  if (!c->have_results) return fail(c, BPM_ESTATE, "bpm_get_trajectory: no synchronised run");
+  if (id < 0 || id >= (int)c->slot_of.size() || c->slot_of[id] < 0) return fail(c, BPM_EINVAL, "bpm_get_trajectory: bad instance id");
+  const int s = c->slot_of[id];
+  const int64_t nt = std::min<int64_t>({c->h_inst_out[s].n_traj, cap, (int64_t)c->run_traj_cap});
+  if (nt > 0)
+    HIPCHK(c, hipMemcpy(out, c->d_traj + (size_t)s * c->run_traj_cap * kTrajW, sizeof(double) * nt * kTrajW,
+                        hipMemcpyDeviceToHost));
+  *n_written = nt;
+  return BPM_OK;
+}
+
+int bpm_get_m(bpm_ctx* c, int32_t id, double* m_out) {
+  if (!c) return BPM_EINVAL;
+  if (!m_out) return fail(c, BPM_EINVAL, "bpm_get_m: null output");
+  if (!c->have_results) return fail(c, BPM_ESTATE, "bpm_get_m: no synchronised run");
+  if (id < 0 || id >= (int)c->slot_of.size() || c->slot_of[id] < 0) return fail(c, BPM_EINVAL, "bpm_get_m: bad instance id");
+  const int s = c->slot_of[id];
+  const int mi = c->slot_group[s];
+  const int n = c->meshes[mi]->n;
+  const size_t off = (size_t)c->slot_local[s] * 3 * n;
+  if (c->run_precision == 64) {
+    HIPCHK(c, hipMemcpy(m_out, reinterpret_cast<double*>(c->group_m[mi]) + off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(3 * (size_t)n);
+    HIPCHK(c, hipMemcpy(tmp.data(), reinterpret_cast<float*>(c->group_m[mi]) + off, sizeof(float) * 3 * n, hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < tmp.size(); ++q) m_out[q] = tmp[q];
+  }
+  return BPM_OK;
+}
+
+int bpm_last_run_info(bpm_ctx* c, double* kernel_ms, int32_t* grid, int32_t* wg_per_group) {
+  if (!c) return BPM_EINVAL;
+  if (kernel_ms) *kernel_ms = c->kernel_ms;
+  if (grid) *grid = c->run_grid;
+  if (wg_per_group) *wg_per_group = c->run_G;
+  return BPM_OK;
+}
+
+}  // extern "C"

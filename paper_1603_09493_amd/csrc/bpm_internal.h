@@ -1,0 +1,148 @@
+// Internal data model of the batched FE-LLG island solver (not part of the public ABI).
+//
+// A *mesh group* holds the geometry shared by its instances: P1 stiffness K and charge operator
+// D on one CSR pattern, the transposed charge values DT on the same pattern, lumped node
+// volumes, interface partners and areas, and the dense demag operator S.  An *instance* is one
+// island simulation on a group (its own material, field schedule, position, seed).  A *system*
+// is the unit that shares a clock: one instance, or several dipole-coupled instances.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bpm_llg.h"
+
+namespace bpm {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4.0e-7 * kPi;          // T m / A
+constexpr double kGammaE = 1.76085963023e11;   // rad / (s T)
+constexpr double kBoltzmann = 1.380649e-23;    // J / K
+
+constexpr int kMaxSysPerGroup = 64;   // adaptive-control state is replicated in LDS per group
+constexpr int kMaxInstPerGroup = 64;
+constexpr int kBlock = 256;           // threads per workgroup of the stepping kernels
+constexpr int kTrajW = 9;             // trajectory sample width
+
+// Host-side mesh group (geometry + device copies).
+struct MeshGroup {
+  int n = 0, ntet = 0, nnz = 0, nif = 0;
+  std::vector<double> x, y, z;            // node coordinates
+  std::vector<int32_t> tet, layer, iface;
+  std::vector<int32_t> rowptr, col;       // CSR pattern: nodes sharing a tetrahedron
+  std::vector<double> K, D, DT;           // stiffness, charge operator [nnz][3], transpose [nnz][3]
+  std::vector<double> V, tetV;            // lumped node volumes, tet volumes
+  std::vector<int32_t> partner;           // interface partner node or -1
+  std::vector<double> aif;                // lumped interface area per node (0 off the interface)
+  std::vector<int32_t> n2t_ptr, n2t;      // node -> tets
+  double centroid[3] = {0, 0, 0};
+  double vol_layer[2] = {0, 0};
+  // device copies
+  double* dS64 = nullptr;                 // [n][n]
+  float* dS32 = nullptr;
+  bool S_ready = false;
+};
+
+// Per-instance constants in the form the kernels use.
+struct InstConst {
+  double Ms[2];
+  double cex[2];      // 2 A / Ms      (B_ex = -cex / V_i (K m)_i)
+  double can[2];      // 2 K / Ms      (B_an = can (m.u) u)
+  double axis[2][3];
+  double cint[2];     // A_int / (delta Ms)   (B_int = cint a_i / V_i m_partner)
+  double alpha, gp;   // damping and gamma/(1+alpha^2)
+  double A[2], K[2], Jint;   // for energies
+  // field
+  int32_t fkind, pad_;
+  double B_peak, dir[3], t_rise, v[3], x_off[3], L_grad, W_pole, B_ext[3];
+  double off[3];      // island position offset
+  uint32_t key[2];    // Philox key (seed low, seed high)
+  int32_t group, sys, local;   // mesh group, system, index within the group
+  int32_t pad2_;
+};
+
+struct Instance {
+  int32_t mesh = 0;
+  InstConst c{};
+  std::vector<double> m0;   // [3][n]
+  int32_t sys = -1;         // -1: own system
+  bool coupled = false;
+};
+
+// Per-system outputs written by the kernels.
+struct SysOut {
+  int32_t status, pad_;
+  double t_reached;
+  int64_t n_accept, n_reject;
+  double dt_min_used, dt_max_used, max_norm_dev;
+};
+
+// Per-instance outputs.
+struct InstOut {
+  int32_t crossed, switched;
+  double t_sw, mz_soft, mz_hard;
+  int64_t n_traj;
+};
+
+// Kernel view of one mesh group for a run.
+template <typename real>
+struct GroupView {
+  int n, nnz, R, nsys;
+  int ldS;                    // row stride of S (n rounded up to a multiple of 16)
+  int wg0, G;                 // first workgroup, workgroups per group
+  int inst0, sys0;            // first instance / system (contiguous)
+  const int32_t* rowptr;
+  const int32_t* col;
+  const real* K;
+  const real* D;              // [nnz][3]
+  const real* DT;             // [nnz][3]
+  const real* S;              // [n][n]
+  const real* V;
+  const int32_t* layer;
+  const int32_t* partner;
+  const real* aif;
+  const double* x;            // coordinates in double (field evaluation)
+  const double* y;
+  const double* z;
+  double cen[3];
+  double Vsoft, Vhard;
+  // state, per instance r at offset r * stride
+  real* m;                    // [R][3][n]
+  real* ys;                   // [R][3][n] stage input
+  real* k;                    // [R][7][3][n]
+  real* yex;                  // [R][3][n]
+  real* b;                    // [R][n]
+  real* u;                    // [R][n]
+  unsigned long long* bar;    // group barrier counter
+};
+
+struct SysView {
+  int32_t inst0, count, coupled, pad_;
+};
+
+struct RunParams {
+  int32_t ngroups, ninst, nsys, integrator;
+  double t_end, dt0, dt_fixed, rtol, atol, dt_min, temperature;
+  int64_t max_steps;
+  int32_t save_every, traj_cap;
+  const InstConst* inst;
+  const SysView* sys;
+  SysOut* sys_out;
+  InstOut* inst_out;
+  double* traj;               // [ninst][traj_cap][9]
+  double* err_acc;            // [nsys][2]
+  double* obs_acc;            // [ninst][2][6]: sum V mz soft, sum V mz hard, sum w m (3), max dev
+  double* mom_acc;            // [ninst][2][3]
+  const int2* wg_map;         // blockIdx -> (group, local wg)
+};
+
+std::string hip_err_string(hipError_t e);
+
+// assembly.cpp
+int assemble_mesh(MeshGroup& g, std::string& err);
+// demag.hip
+int demag_assemble_device(MeshGroup& g, double beta, hipStream_t stream, std::string& err);
+
+}  // namespace bpm
