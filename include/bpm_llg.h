@@ -171,6 +171,53 @@ int bpm_get_m(bpm_ctx* ctx, int32_t id, double* m_out);
 /* Wall time of the last run's kernels (ms, HIP events on the run stream) and launch data. */
 int bpm_last_run_info(bpm_ctx* ctx, double* kernel_ms, int32_t* grid, int32_t* wg_per_group);
 
+
+/* ------------------------------------------------------------------------------------------ */
+/* Learned screen                                                                             */
+/* ------------------------------------------------------------------------------------------ */
+/* The paper's optimizer proposes each new design from a Gaussian-process surrogate of the
+ * objective and evaluates the one with the largest expected improvement (Sec. II.A).  Here a
+ * multilayer perceptron 12 -> 256 -> 256 -> 256 -> 256 -> 3 (exact-erf GELU between layers),
+ * trained on the solver's own results, scores whole rounds of candidates; the batched solver
+ * re-verifies the best.  Outputs: z-scored switching field, z-scored log switching time, logit
+ * of the switching probability.  Every operand of a matrix product is rounded to bfloat16 (round
+ * to nearest even) and accumulated in FP32 on the matrix cores; bias, GELU, loss and Adam are
+ * FP32.  Parameters are one flat FP32 vector: per layer W [out][in] row-major, then b [out].
+ * X, Y, T, mask, score and idx arguments are DEVICE pointers; theta and grads are host pointers. */
+typedef struct bpm_mlp bpm_mlp;
+
+/* Number of parameters of the network (201475). */
+int bpm_mlp_num_params(void);
+/* Creates a network able to train on batches up to max_batch; theta (host, may be NULL = zeros). */
+int bpm_mlp_create(bpm_ctx* ctx, int32_t max_batch, const float* theta, bpm_mlp** out);
+void bpm_mlp_destroy(bpm_mlp* net);
+/* Replaces the parameters (and resets the Adam moments and step count). */
+int bpm_mlp_set_params(bpm_mlp* net, const float* theta);
+int bpm_mlp_get_params(bpm_mlp* net, float* theta);
+/* Y [n][3] = net(X [n][12]) with the fused inference kernel (activations stay on chip). */
+int bpm_mlp_predict(bpm_mlp* net, const float* X, float* Y, int64_t n, void* hip_stream);
+/* Loss L = (1/B) sum_b [ mask_b ((y0-t0)^2 + (y1-t1)^2) + softplus(y2) - t2 y2 ] and its gradient
+ * (host outputs, either may be NULL), without changing the parameters.  T: [B][3], mask: [B]. */
+int bpm_mlp_grads(bpm_mlp* net, const float* X, const float* T, const uint8_t* mask, int32_t batch,
+                  float* loss, float* grads);
+/* One Adam step (beta = 0.9, 0.999, eps = 1e-8) on the same loss; loss (host, may be NULL)
+ * receives the loss before the step (this synchronises the stream). */
+int bpm_mlp_train_step(bpm_mlp* net, const float* X, const float* T, const uint8_t* mask,
+                       int32_t batch, float lr, float* loss, void* hip_stream);
+/* n candidate designs, scaled features X [n][12] in (-1, 1): X[i][f] = 2u - 1, u = (w + 1/2) 2^-32,
+ * w the words of Philox4x32-10 with key (seed low, seed high) and counter (i low, i high, f/4, 0). */
+int bpm_sample_designs(bpm_ctx* ctx, uint64_t seed, int64_t n, float* X, void* hip_stream);
+/* Indices of the k largest scores, ordered by (score descending, index ascending); NaN ranks
+ * lowest.  0 < k <= min(n, 16384), n < 2^31.  idx: device int64 [k]. */
+int bpm_topk(bpm_mlp* net, const float* score, int64_t n, int64_t k, int64_t* idx, void* hip_stream);
+/* One screening round: sample n designs (as bpm_sample_designs), predict, score = predicted
+ * switching logit where the thermal-stability proxy (K_s V_s + K_h V_h) / (kB 300 K) is at least
+ * min_stability (else -inf), keep the top k.  lo/hi (host [12]) map X back to the physical design
+ * x = lo + (hi - lo)(X + 1)/2 with the feature order d, t_soft, t_hard, Ms_soft, Ms_hard, K_soft,
+ * K_hard, A_int, psi, B_peak, alpha, t_rise.  X [n][12], Y [n][3], score [n], idx [k] on device. */
+int bpm_screen(bpm_mlp* net, uint64_t seed, int64_t n, int64_t k, const double* lo, const double* hi,
+               double min_stability, float* X, float* Y, float* score, int64_t* idx, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,11 @@ SYMBOLS = [
     "bpm_run", "bpm_sync", "bpm_get_results", "bpm_get_trajectory", "bpm_get_m", "bpm_last_run_info",
 ]
 
+EXTRA_SYMBOLS = [
+    "bpm_mlp_num_params", "bpm_mlp_create", "bpm_mlp_destroy", "bpm_mlp_set_params", "bpm_mlp_get_params",
+    "bpm_mlp_predict", "bpm_mlp_grads", "bpm_mlp_train_step", "bpm_sample_designs", "bpm_topk", "bpm_screen",
+]
+
 _lib = None
 
 
@@ -99,9 +104,21 @@ def lib():
     L.bpm_get_trajectory.argtypes = [P, I32, P, I64, C.POINTER(I64)]
     L.bpm_get_m.argtypes = [P, I32, P]
     L.bpm_last_run_info.argtypes = [P, C.POINTER(D), C.POINTER(I32), C.POINTER(I32)]
-    for name in SYMBOLS:
+    L.bpm_mlp_num_params.argtypes = []
+    L.bpm_mlp_create.argtypes = [P, I32, P, C.POINTER(P)]
+    L.bpm_mlp_destroy.argtypes = [P]
+    L.bpm_mlp_destroy.restype = None
+    L.bpm_mlp_set_params.argtypes = [P, P]
+    L.bpm_mlp_get_params.argtypes = [P, P]
+    L.bpm_mlp_predict.argtypes = [P, P, P, I64, P]
+    L.bpm_mlp_grads.argtypes = [P, P, P, P, I32, P, P]
+    L.bpm_mlp_train_step.argtypes = [P, P, P, P, I32, C.c_float, P, P]
+    L.bpm_sample_designs.argtypes = [P, C.c_uint64, I64, P, P]
+    L.bpm_topk.argtypes = [P, P, I64, I64, P, P]
+    L.bpm_screen.argtypes = [P, C.c_uint64, I64, I64, P, P, D, P, P, P, P, P]
+    for name in SYMBOLS + EXTRA_SYMBOLS:
         fn = getattr(L, name)
-        if name not in ("bpm_destroy", "bpm_last_error"):
+        if name not in ("bpm_destroy", "bpm_last_error", "bpm_mlp_destroy"):
             fn.restype = C.c_int
     _lib = L
     return L
@@ -241,6 +258,78 @@ class Context:
         ms = C.c_double(); grid = C.c_int32(); G = C.c_int32()
         self._check(self.L.bpm_last_run_info(self.h, C.byref(ms), C.byref(grid), C.byref(G)))
         return dict(kernel_ms=ms.value, grid=grid.value, wg_per_group=G.value)
+
+
+def _dp(x):
+    """Device pointer of a torch tensor (or an int address)."""
+    return C.c_void_p(x if isinstance(x, int) else x.data_ptr())
+
+
+class Mlp:
+    """Surrogate MLP 12 -> 4 x 256 -> 3 on the GPU (bpm_mlp).  Device buffers are torch tensors."""
+
+    def __init__(self, ctx: Context, max_batch: int = 4096, theta=None):
+        self.ctx, self.L = ctx, ctx.L
+        self.h = C.c_void_p()
+        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float32)
+        ctx._check(self.L.bpm_mlp_create(ctx.h, int(max_batch), _p(th), C.byref(self.h)))
+        self.n_params = self.L.bpm_mlp_num_params()
+
+    def close(self):
+        if self.h:
+            self.L.bpm_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == self.n_params
+        self.ctx._check(self.L.bpm_mlp_set_params(self.h, _p(th)))
+
+    def get_params(self):
+        out = np.empty(self.n_params, np.float32)
+        self.ctx._check(self.L.bpm_mlp_get_params(self.h, _p(out)))
+        return out
+
+    def predict(self, X, Y, n=None, stream=None):
+        n = X.shape[0] if n is None else n
+        self.ctx._check(self.L.bpm_mlp_predict(self.h, _dp(X), _dp(Y), int(n), None if stream is None else C.c_void_p(stream)))
+
+    def grads(self, X, T, mask, batch=None):
+        batch = X.shape[0] if batch is None else batch
+        loss = C.c_float()
+        g = np.empty(self.n_params, np.float32)
+        self.ctx._check(self.L.bpm_mlp_grads(self.h, _dp(X), _dp(T), _dp(mask), int(batch), C.byref(loss), _p(g)))
+        return loss.value, g
+
+    def train_step(self, X, T, mask, lr, batch=None, want_loss=True, stream=None):
+        batch = X.shape[0] if batch is None else batch
+        loss = C.c_float()
+        self.ctx._check(self.L.bpm_mlp_train_step(self.h, _dp(X), _dp(T), _dp(mask), int(batch), float(lr),
+                                                  C.byref(loss) if want_loss else None,
+                                                  None if stream is None else C.c_void_p(stream)))
+        return loss.value if want_loss else None
+
+    def topk(self, score, k, idx, n=None, stream=None):
+        n = score.shape[0] if n is None else n
+        self.ctx._check(self.L.bpm_topk(self.h, _dp(score), int(n), int(k), _dp(idx),
+                                        None if stream is None else C.c_void_p(stream)))
+
+    def screen(self, seed, n, k, lo, hi, min_stability, X, Y, score, idx, stream=None):
+        lo = np.ascontiguousarray(lo, dtype=np.float64); hi = np.ascontiguousarray(hi, dtype=np.float64)
+        self.ctx._check(self.L.bpm_screen(self.h, C.c_uint64(int(seed)), int(n), int(k), _p(lo), _p(hi),
+                                          float(min_stability), _dp(X), _dp(Y), _dp(score), _dp(idx),
+                                          None if stream is None else C.c_void_p(stream)))
+
+
+def sample_designs(ctx: Context, seed, n, X, stream=None):
+    ctx._check(ctx.L.bpm_sample_designs(ctx.h, C.c_uint64(int(seed)), int(n), _dp(X),
+                                        None if stream is None else C.c_void_p(stream)))
 
 
 def nan_to_none(x):

@@ -10,6 +10,8 @@
 #include <vector>
 
 #include "bpm_internal.h"
+#include "mlp_internal.h"
+#include "heun_internal.h"
 
 namespace bpm {
 
@@ -73,6 +75,9 @@ struct bpm_ctx {
   bool run_pending = false, have_results = false;
   int run_precision = 64, run_traj_cap = 0, run_grid = 0, run_G = 0;
   int run_ninst = 0, run_nsys = 0;
+  bool run_rfast = false;                  // state layout [3][N][R] (Heun path)
+  std::vector<int32_t> slot_R;             // run slot -> R of its group (Heun path)
+  hipGraphExec_t graph_exec = nullptr;
   std::vector<int32_t> inst_order;         // run slot -> instance id
   std::vector<int32_t> slot_of;            // instance id -> run slot
   std::vector<int32_t> slot_group;         // run slot -> mesh id
@@ -89,6 +94,9 @@ struct bpm_ctx {
   std::vector<InstOut> h_inst_out;
   std::vector<double> h_energy;
   float kernel_ms = 0.f;
+  double* heun_obs = nullptr;
+  long long heun_nsteps = 0;
+  double heun_dt = 0.0, heun_t_end = 0.0;
 };
 
 static int fail(bpm_ctx* c, int code, const std::string& msg) {
@@ -131,6 +139,7 @@ void bpm_destroy(bpm_ctx* c) {
     if (m->dS32) hipFree(m->dS32);
   }
   c->mesh_arena.clear();
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
@@ -555,6 +564,152 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   return BPM_OK;
 }
 
+
+template <typename real>
+static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
+  Arena& A = c->run;
+  A.clear();
+  const int nm = (int)c->meshes.size();
+  std::vector<std::vector<int32_t>> by_mesh(nm);
+  for (int32_t i = 0; i < (int32_t)c->insts.size(); ++i) {
+    if (c->insts[i].coupled) return fail(c, BPM_EINVAL, "bpm_run: dipole coupling is not available with BPM_HEUN");
+    by_mesh[c->insts[i].mesh].push_back(i);
+  }
+  c->inst_order.clear();
+  c->slot_of.assign(c->insts.size(), -1);
+  c->slot_group.clear(); c->slot_local.clear(); c->slot_R.clear();
+  c->group_inst0.assign(nm, -1);
+  c->group_m.assign(nm, nullptr);
+  std::vector<InstConst> ic;
+  std::vector<HeunGroup<real>> hg;
+  std::vector<int2> bmap;
+  std::vector<int4> tmap;
+  int Rmax = 1;
+  for (int mi = 0; mi < nm; ++mi) {
+    auto& v = by_mesh[mi];
+    if (v.empty()) continue;
+    const MeshGroup& g = *c->meshes[mi];
+    const DevGeom<real>& d = std::is_same<real, double>::value
+                                 ? *reinterpret_cast<const DevGeom<real>*>(&c->dmeshes[mi]->g64)
+                                 : *reinterpret_cast<const DevGeom<real>*>(&c->dmeshes[mi]->g32);
+    const int R = (int)v.size();
+    Rmax = std::max(Rmax, R);
+    HeunGroup<real> h{};
+    h.n = g.n; h.R = R; h.ldS = (g.n + 15) / 16 * 16; h.inst0 = (int)ic.size();
+    h.rowptr = d.rowptr; h.col = d.col; h.K = d.K; h.D = d.D; h.DT = d.DT;
+    h.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
+    h.V = d.V; h.layer = d.layer; h.partner = d.partner; h.aif = d.aif; h.x = d.x; h.y = d.y;
+    h.Vsoft = g.vol_layer[0]; h.Vhard = g.vol_layer[1];
+    const size_t cs = (size_t)g.n * R;
+    HIPCHK(c, A.alloc(&h.m, 3 * cs));
+    HIPCHK(c, A.alloc(&h.yt, 3 * cs));
+    HIPCHK(c, A.alloc(&h.k1, 3 * cs));
+    HIPCHK(c, A.alloc(&h.mnext, 3 * cs));
+    HIPCHK(c, A.alloc(&h.yex, 3 * cs));
+    HIPCHK(c, A.alloc(&h.b, cs));
+    HIPCHK(c, A.alloc(&h.u, cs));
+    std::vector<real> m0(3 * cs);
+    c->group_inst0[mi] = (int32_t)c->inst_order.size();
+    for (int r = 0; r < R; ++r) {
+      const int id = v[r];
+      const auto& src = c->insts[id].m0;
+      for (int comp = 0; comp < 3; ++comp)
+        for (int i = 0; i < g.n; ++i) m0[comp * cs + (size_t)i * R + r] = (real)src[(size_t)comp * g.n + i];
+      c->slot_of[id] = (int32_t)c->inst_order.size();
+      c->inst_order.push_back(id);
+      c->slot_group.push_back(mi);
+      c->slot_local.push_back(r);
+      c->slot_R.push_back(R);
+      InstConst k = c->insts[id].c;
+      k.group = (int32_t)hg.size(); k.sys = (int32_t)ic.size(); k.local = r;
+      ic.push_back(k);
+    }
+    HIPCHK(c, hipMemcpyAsync(h.m, m0.data(), sizeof(real) * m0.size(), hipMemcpyHostToDevice, stream));
+    c->group_m[mi] = h.m;
+    const int gi = (int)hg.size();
+    const long nb = ((long)g.n * R + 255) / 256;
+    for (long b = 0; b < nb; ++b) bmap.push_back(make_int2(gi, (int)b));
+    for (int m0r = 0; m0r < g.n; m0r += 64)
+      for (int n0 = 0; n0 < R; n0 += 64) tmap.push_back(make_int4(gi, m0r, n0, 0));
+    hg.push_back(h);
+  }
+  const int ng = (int)hg.size(), ninst = (int)ic.size();
+  if (ng == 0) return fail(c, BPM_ESTATE, "bpm_run: no instances");
+  if (bmap.size() > 0x7fffffffu || tmap.size() > 0x7fffffffu) return fail(c, BPM_EINVAL, "bpm_run: batch too large");
+  HeunGroup<real>* d_groups;
+  int2* d_bmap;
+  int4* d_tmap;
+  InstConst* d_ic;
+  unsigned long long* d_step;
+  double* d_obs;
+  HIPCHK(c, A.alloc(&d_groups, ng));
+  HIPCHK(c, A.alloc(&d_bmap, bmap.size()));
+  HIPCHK(c, A.alloc(&d_tmap, tmap.size()));
+  HIPCHK(c, A.alloc(&d_ic, ninst));
+  HIPCHK(c, A.alloc(&d_step, 1));
+  HIPCHK(c, A.alloc(&d_obs, 2 * (size_t)ninst));
+  HIPCHK(c, A.alloc(&c->d_energy, ninst));
+  HIPCHK(c, hipMemcpyAsync(d_groups, hg.data(), sizeof(HeunGroup<real>) * ng, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_bmap, bmap.data(), sizeof(int2) * bmap.size(), hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_tmap, tmap.data(), sizeof(int4) * tmap.size(), hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_ic, ic.data(), sizeof(InstConst) * ninst, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemsetAsync(d_step, 0, sizeof(unsigned long long), stream));
+  HeunLaunch<real> L{d_groups, d_bmap, d_tmap, d_ic, (int)bmap.size(), (int)tmap.size(),
+                     HeunParams{o->dt_fixed, o->dt_fixed, o->temperature, d_step}};
+  const long long nsteps = (long long)std::ceil(o->t_end / o->dt_fixed - 1e-9);
+  const double h_last = o->t_end - (double)(nsteps - 1) * o->dt_fixed;
+  const bool clip = nsteps > 0 && std::fabs(h_last - o->dt_fixed) > 1e-12 * o->dt_fixed;
+  const long long nfull = clip ? nsteps - 1 : nsteps;
+  HIPCHK(c, hipEventRecord(c->ev0, stream));
+  if (nfull > 0) {
+    // one regular step captured once, replayed nfull times
+    hipGraph_t graph = nullptr;
+    if (c->graph_exec) {
+      hipGraphExecDestroy(c->graph_exec);
+      c->graph_exec = nullptr;
+    }
+    HIPCHK(c, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = heun_step<real>(L, stream);
+    hipError_t ee = hipStreamEndCapture(stream, &graph);
+    if (ce != hipSuccess || ee != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return fail(c, BPM_EHIP, std::string("Heun graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(c, BPM_EHIP, std::string("Heun graph instantiate: ") + hipGetErrorString(ie));
+    for (long long st = 0; st < nfull; ++st) HIPCHK(c, hipGraphLaunch(c->graph_exec, stream));
+  }
+  if (clip) {
+    HeunLaunch<real> Ll = L;
+    Ll.params.h = h_last;
+    HIPCHK(c, heun_step<real>(Ll, stream));
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, stream));
+  HIPCHK(c, heun_observe_launch<real>(L, ng, Rmax, d_obs, stream));
+  // results in the same shapes as the DP5 path (one system per instance)
+  c->run_ninst = ninst;
+  c->run_nsys = ninst;
+  c->sys_of_slot.resize(ninst);
+  for (int s2 = 0; s2 < ninst; ++s2) c->sys_of_slot[s2] = s2;
+  c->h_sys_out.assign(ninst, SysOut{});
+  c->h_inst_out.assign(ninst, InstOut{});
+  c->h_energy.assign(ninst, NAN);
+  c->heun_obs = d_obs;
+  c->heun_nsteps = nsteps;
+  c->heun_dt = o->dt_fixed;
+  c->heun_t_end = o->t_end;
+  c->run_traj_cap = 0;
+  c->run_precision = sizeof(real) == 8 ? 64 : 32;
+  c->run_stream = stream;
+  c->run_rfast = true;
+  c->run_pending = true;
+  c->have_results = false;
+  c->run_grid = L.nblk;
+  c->run_G = 1;
+  return BPM_OK;
+}
+
 extern "C" {
 
 int bpm_run(bpm_ctx* c, const bpm_run_opts* o, void* hip_stream) {
@@ -562,8 +717,10 @@ int bpm_run(bpm_ctx* c, const bpm_run_opts* o, void* hip_stream) {
   if (!o) return fail(c, BPM_EINVAL, "bpm_run: null options");
   if (c->run_pending) return fail(c, BPM_ESTATE, "bpm_run: previous run not synchronised");
   if (o->precision != 32 && o->precision != 64) return fail(c, BPM_EINVAL, "bpm_run: precision must be 32 or 64");
-  if (o->integrator != BPM_DP45 && o->integrator != BPM_DP5_FIXED)
-    return fail(c, BPM_EINVAL, "bpm_run: integrator not supported by this entry point");
+  if (o->integrator != BPM_DP45 && o->integrator != BPM_DP5_FIXED && o->integrator != BPM_HEUN)
+    return fail(c, BPM_EINVAL, "bpm_run: unknown integrator");
+  if (o->integrator == BPM_HEUN && (!(o->dt_fixed > 0.0) || !(o->temperature >= 0.0)))
+    return fail(c, BPM_EINVAL, "bpm_run: BPM_HEUN needs dt_fixed > 0 and temperature >= 0");
   if (!(o->t_end >= 0.0) || !std::isfinite(o->t_end)) return fail(c, BPM_EINVAL, "bpm_run: t_end must be finite and >= 0");
   if (o->integrator == BPM_DP5_FIXED && !(o->dt_fixed > 0.0)) return fail(c, BPM_EINVAL, "bpm_run: dt_fixed must be > 0");
   if (o->integrator == BPM_DP45 && (!(o->dt0 > 0.0) || !(o->rtol > 0.0) || !(o->atol > 0.0)))
@@ -572,6 +729,8 @@ int bpm_run(bpm_ctx* c, const bpm_run_opts* o, void* hip_stream) {
   if (c->insts.empty()) return fail(c, BPM_ESTATE, "bpm_run: no instances");
   hipSetDevice(c->device);
   hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->own_stream;
+  c->run_rfast = false;
+  if (o->integrator == BPM_HEUN) return o->precision == 64 ? run_heun_typed<double>(c, o, s) : run_heun_typed<float>(c, o, s);
   return o->precision == 64 ? run_typed<double>(c, o, s) : run_typed<float>(c, o, s);
 }
 
@@ -582,6 +741,29 @@ int bpm_sync(bpm_ctx* c) {
   c->run_pending = false;
   HIPCHK(c, hipStreamSynchronize(c->run_stream));
   HIPCHK(c, hipEventElapsedTime(&c->kernel_ms, c->ev0, c->ev1));
+  if (c->run_rfast) {
+    std::vector<double> obs(2 * (size_t)c->run_ninst);
+    HIPCHK(c, hipMemcpy(obs.data(), c->heun_obs, sizeof(double) * obs.size(), hipMemcpyDeviceToHost));
+    for (int s2 = 0; s2 < c->run_ninst; ++s2) {
+      SysOut& so = c->h_sys_out[s2];
+      InstOut& io = c->h_inst_out[s2];
+      const bool finite = std::isfinite(obs[2 * s2]) && std::isfinite(obs[2 * s2 + 1]);
+      so.status = finite ? BPM_OK : BPM_ENONFINITE;
+      so.t_reached = c->heun_t_end;
+      so.n_accept = c->heun_nsteps;
+      so.n_reject = 0;
+      so.dt_min_used = so.dt_max_used = c->heun_dt;
+      so.max_norm_dev = 0.0;
+      io.crossed = 0;
+      io.t_sw = NAN;
+      io.mz_soft = obs[2 * s2];
+      io.mz_hard = obs[2 * s2 + 1];
+      io.switched = io.mz_hard < 0.0;
+      io.n_traj = 0;
+    }
+    c->have_results = true;
+    return BPM_OK;
+  }
   c->h_sys_out.resize(c->run_nsys);
   c->h_inst_out.resize(c->run_ninst);
   c->h_energy.resize(c->run_ninst);
@@ -655,6 +837,21 @@ int bpm_get_m(bpm_ctx* c, int32_t id, double* m_out) {
   const int s = c->slot_of[id];
   const int mi = c->slot_group[s];
   const int n = c->meshes[mi]->n;
+  if (c->run_rfast) {
+    const int R = c->slot_R[s], r = c->slot_local[s];
+    const size_t cnt = 3 * (size_t)n * R;
+    std::vector<double> all(cnt);
+    if (c->run_precision == 64) {
+      HIPCHK(c, hipMemcpy(all.data(), c->group_m[mi], sizeof(double) * cnt, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(cnt);
+      HIPCHK(c, hipMemcpy(tmp.data(), c->group_m[mi], sizeof(float) * cnt, hipMemcpyDeviceToHost));
+      for (size_t q = 0; q < cnt; ++q) all[q] = tmp[q];
+    }
+    for (int comp = 0; comp < 3; ++comp)
+      for (int i = 0; i < n; ++i) m_out[(size_t)comp * n + i] = all[(size_t)comp * n * R + (size_t)i * R + r];
+    return BPM_OK;
+  }
   const size_t off = (size_t)c->slot_local[s] * 3 * n;
   if (c->run_precision == 64) {
     HIPCHK(c, hipMemcpy(m_out, reinterpret_cast<double*>(c->group_m[mi]) + off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
@@ -671,6 +868,179 @@ int bpm_last_run_info(bpm_ctx* c, double* kernel_ms, int32_t* grid, int32_t* wg_
   if (kernel_ms) *kernel_ms = c->kernel_ms;
   if (grid) *grid = c->run_grid;
   if (wg_per_group) *wg_per_group = c->run_G;
+  return BPM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================================
+// Surrogate MLP and screening
+// ===========================================================================================
+struct bpm_mlp {
+  bpm_ctx* ctx = nullptr;
+  bpm::Mlp net;
+  bpm::ScreenScratch sc;
+  bpm::Arena arena;
+};
+
+extern "C" {
+
+int bpm_mlp_num_params(void) { return (int)kMlpParams; }
+
+int bpm_mlp_create(bpm_ctx* c, int32_t max_batch, const float* theta, bpm_mlp** out) {
+  if (!c) return BPM_EINVAL;
+  if (!out || max_batch <= 0) return fail(c, BPM_EINVAL, "bpm_mlp_create: bad argument");
+  hipSetDevice(c->device);
+  auto* M = new bpm_mlp();
+  M->ctx = c;
+  Mlp& n = M->net;
+  n.max_batch = max_batch;
+  Arena& A = M->arena;
+  const long B = max_batch;
+  hipError_t e = hipSuccess;
+  auto al = [&](auto** p, size_t cnt) {
+    if (e == hipSuccess) e = A.alloc(p, cnt);
+  };
+  al(&n.theta, kMlpParams); al(&n.m, kMlpParams); al(&n.v, kMlpParams); al(&n.grad, kMlpParams);
+  for (int l = 0; l < 5; ++l) al(&n.Z[l], B * mlp_size(l + 1));
+  for (int l = 0; l < 4; ++l) al(&n.Aout[l], B * kMlpHidden);
+  al(&n.dZ, B * kMlpOut); al(&n.dA, B * kMlpHidden); al(&n.dZh, B * kMlpHidden); al(&n.dZh2, B * kMlpHidden);
+  al(&n.d_loss, 1);
+  const int kp[5] = {32, 256, 256, 256, 256}, op[5] = {256, 256, 256, 256, 16};
+  for (int l = 0; l < 5; ++l) {
+    al(&n.dev.w[l], (size_t)kp[l] * op[l]);
+    al(&n.dev.b[l], (size_t)op[l]);
+  }
+  if (e != hipSuccess) {
+    delete M;
+    return fail(c, BPM_ENOMEM, std::string("bpm_mlp_create: ") + hipGetErrorString(e));
+  }
+  hipMemset(n.m, 0, sizeof(float) * kMlpParams);
+  hipMemset(n.v, 0, sizeof(float) * kMlpParams);
+  if (theta) hipMemcpy(n.theta, theta, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+  else hipMemset(n.theta, 0, sizeof(float) * kMlpParams);
+  mlp_pack(n, c->own_stream);
+  if ((e = hipStreamSynchronize(c->own_stream)) != hipSuccess) {
+    delete M;
+    return fail(c, BPM_EHIP, std::string("bpm_mlp_create: ") + hipGetErrorString(e));
+  }
+  *out = M;
+  return BPM_OK;
+}
+
+void bpm_mlp_destroy(bpm_mlp* M) {
+  if (!M) return;
+  hipSetDevice(M->ctx->device);
+  hipDeviceSynchronize();
+  if (M->sc.hist) hipFree(M->sc.hist);
+  if (M->sc.state) hipFree(M->sc.state);
+  if (M->sc.cand) hipFree(M->sc.cand);
+  if (M->sc.blk) hipFree(M->sc.blk);
+  delete M;
+}
+
+int bpm_mlp_set_params(bpm_mlp* M, const float* theta) {
+  if (!M) return BPM_EINVAL;
+  bpm_ctx* c = M->ctx;
+  if (!theta) return fail(c, BPM_EINVAL, "bpm_mlp_set_params: null");
+  hipSetDevice(c->device);
+  HIPCHK(c, hipMemcpy(M->net.theta, theta, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(M->net.m, 0, sizeof(float) * kMlpParams));
+  HIPCHK(c, hipMemset(M->net.v, 0, sizeof(float) * kMlpParams));
+  M->net.step = 0;
+  HIPCHK(c, mlp_pack(M->net, c->own_stream));
+  HIPCHK(c, hipStreamSynchronize(c->own_stream));
+  return BPM_OK;
+}
+
+int bpm_mlp_get_params(bpm_mlp* M, float* theta) {
+  if (!M) return BPM_EINVAL;
+  bpm_ctx* c = M->ctx;
+  if (!theta) return fail(c, BPM_EINVAL, "bpm_mlp_get_params: null");
+  hipSetDevice(c->device);
+  HIPCHK(c, hipDeviceSynchronize());
+  HIPCHK(c, hipMemcpy(theta, M->net.theta, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+  return BPM_OK;
+}
+
+int bpm_mlp_predict(bpm_mlp* M, const float* X, float* Y, int64_t n, void* stream) {
+  if (!M) return BPM_EINVAL;
+  bpm_ctx* c = M->ctx;
+  if (n < 0 || (n > 0 && (!X || !Y))) return fail(c, BPM_EINVAL, "bpm_mlp_predict: bad argument");
+  hipSetDevice(c->device);
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
+  HIPCHK(c, mlp_predict(M->net, X, Y, (long)n, s));
+  return BPM_OK;
+}
+
+int bpm_mlp_grads(bpm_mlp* M, const float* X, const float* T, const uint8_t* mask, int32_t batch, float* loss,
+                  float* grads) {
+  if (!M) return BPM_EINVAL;
+  bpm_ctx* c = M->ctx;
+  if (!X || !T || !mask || batch <= 0 || batch > M->net.max_batch) return fail(c, BPM_EINVAL, "bpm_mlp_grads: bad argument");
+  hipSetDevice(c->device);
+  HIPCHK(c, mlp_forward_backward(M->net, X, T, mask, batch, c->own_stream));
+  HIPCHK(c, hipStreamSynchronize(c->own_stream));
+  if (loss) {
+    double l = 0;
+    HIPCHK(c, hipMemcpy(&l, M->net.d_loss, sizeof(double), hipMemcpyDeviceToHost));
+    *loss = (float)l;
+  }
+  if (grads) HIPCHK(c, hipMemcpy(grads, M->net.grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+  return BPM_OK;
+}
+
+int bpm_mlp_train_step(bpm_mlp* M, const float* X, const float* T, const uint8_t* mask, int32_t batch, float lr,
+                       float* loss, void* stream) {
+  if (!M) return BPM_EINVAL;
+  bpm_ctx* c = M->ctx;
+  if (!X || !T || !mask || batch <= 0 || batch > M->net.max_batch || !(lr > 0.f))
+    return fail(c, BPM_EINVAL, "bpm_mlp_train_step: bad argument");
+  hipSetDevice(c->device);
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
+  HIPCHK(c, mlp_forward_backward(M->net, X, T, mask, batch, s));
+  HIPCHK(c, mlp_adam(M->net, lr, s));
+  if (loss) {
+    double l = 0;
+    HIPCHK(c, hipMemcpyAsync(&l, M->net.d_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    *loss = (float)l;
+  }
+  return BPM_OK;
+}
+
+int bpm_sample_designs(bpm_ctx* c, uint64_t seed, int64_t n, float* X, void* stream) {
+  if (!c) return BPM_EINVAL;
+  if (n < 0 || (n > 0 && !X)) return fail(c, BPM_EINVAL, "bpm_sample_designs: bad argument");
+  hipSetDevice(c->device);
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
+  HIPCHK(c, sample_designs(seed, (long)n, X, s));
+  return BPM_OK;
+}
+
+int bpm_topk(bpm_mlp* M, const float* score, int64_t n, int64_t k, int64_t* idx, void* stream) {
+  if (!M) return BPM_EINVAL;
+  bpm_ctx* c = M->ctx;
+  if (!score || !idx || n <= 0 || n > 0x7fffffffLL || k <= 0 || k > n || k > kTopkMax)
+    return fail(c, BPM_EINVAL, "bpm_topk: need 0 < k <= min(n, 16384), n < 2^31");
+  hipSetDevice(c->device);
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
+  HIPCHK(c, topk_select(score, (long)n, (long)k, idx, M->sc, s));
+  return BPM_OK;
+}
+
+int bpm_screen(bpm_mlp* M, uint64_t seed, int64_t n, int64_t k, const double* lo, const double* hi,
+               double min_stability, float* X, float* Y, float* score, int64_t* idx, void* stream) {
+  if (!M) return BPM_EINVAL;
+  bpm_ctx* c = M->ctx;
+  if (!lo || !hi || !X || !Y || !score || !idx || n <= 0 || n > 0x7fffffffLL || k <= 0 || k > n || k > kTopkMax)
+    return fail(c, BPM_EINVAL, "bpm_screen: bad argument");
+  hipSetDevice(c->device);
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
+  HIPCHK(c, sample_designs(seed, (long)n, X, s));
+  HIPCHK(c, mlp_predict(M->net, X, Y, (long)n, s));
+  HIPCHK(c, screen_score(X, Y, (long)n, lo, hi, min_stability, score, s));
+  HIPCHK(c, topk_select(score, (long)n, (long)k, idx, M->sc, s));
   return BPM_OK;
 }
 

@@ -309,3 +309,17 @@ def random_unit_m(n: int, seed: int, cone: float = math.pi) -> np.ndarray:
     st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
     ph = 2.0 * math.pi * rng.random(n)
     return np.ascontiguousarray(np.stack([st * np.cos(ph), st * np.sin(ph), ct]))
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Seeded He-uniform initial weights (zero biases) of the 12 -> 4x256 -> 3 surrogate, flat
+    FP32 vector in the library's parameter layout (per layer W [out][in], then b [out])."""
+    sizes = (12, 256, 256, 256, 256, 3)
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(sizes) - 1):
+        ni, no = sizes[i], sizes[i + 1]
+        lim = math.sqrt(6.0 / ni)
+        parts.append(rng.uniform(-lim, lim, size=no * ni))
+        parts.append(np.zeros(no))
+    return np.concatenate(parts).astype(np.float32)

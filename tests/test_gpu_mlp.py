@@ -1,0 +1,193 @@
+"""GPU parity of the surrogate MLP, the design sampler and the top-k against the CPU oracle.
+
+Bars: sampler and top-k bit-exact (integer/index work, and the sampler's FP32 values are exact
+functions of the Philox words); MLP forward and gradients within the BF16 tolerance (every GEMM
+operand rounded to bf16 on both sides; the GPU accumulates in FP32, the oracle in FP64, and a
+bf16 rounding of an activation can land on the other side of a tie).
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from paper_1603_09493_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1603_09493_amd import bpm
+    c = bpm.Context(0)
+    yield c
+    c.close()
+
+
+def _case(name, **kw):
+    print(f"[gpu-case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _theta(seed):
+    rng = np.random.default_rng(seed + 100)
+    th = I.mlp_init_params(seed)
+    # non-zero biases so that their gradients and the bias path are exercised
+    off = 0
+    for i in range(5):
+        ni, no = OM.SIZES[i], OM.SIZES[i + 1]
+        off += ni * no
+        th[off:off + no] = 0.1 * rng.standard_normal(no)
+        off += no
+    return th.astype(np.float32)
+
+
+def test_mlp_predict_matches_oracle(ctx, torch_mod):
+    from paper_1603_09493_amd import bpm
+    torch = torch_mod
+    th = _theta(1)
+    net = bpm.Mlp(ctx, 512, th)
+    rng = np.random.default_rng(2)
+    n = 333   # several 128-sample tiles and a ragged tail
+    X = rng.uniform(-1, 1, (n, 12)).astype(np.float32)
+    _case("mlp-predict", n=n)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    net.predict(Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy()
+    Yr, _ = OM.forward(th.astype(np.float64), X.astype(np.float64))
+    scale = np.abs(Yr).max(0)
+    err = np.abs(Y - Yr).max(0) / scale
+    assert np.all(err < 2e-2), err
+    assert np.median(np.abs(Y - Yr) / scale) < 2e-3
+    net.close()
+
+
+def test_mlp_gradients_match_oracle(ctx, torch_mod):
+    from paper_1603_09493_amd import bpm
+    torch = torch_mod
+    th = _theta(3)
+    B = 200
+    net = bpm.Mlp(ctx, 256, th)
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, (B, 12)).astype(np.float32)
+    T = rng.standard_normal((B, 3)).astype(np.float32)
+    T[:, 2] = rng.integers(0, 2, B)
+    mask = rng.integers(0, 2, B).astype(np.uint8)
+    _case("mlp-grads", B=B)
+    L, g = net.grads(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), torch.from_numpy(mask).cuda())
+    Lr, gr = OM.loss_grad(th.astype(np.float64), X.astype(np.float64), T.astype(np.float64), mask)
+    assert abs(L - Lr) <= 2e-3 * abs(Lr)
+    off = 0
+    for i in range(5):
+        ni, no = OM.SIZES[i], OM.SIZES[i + 1]
+        for blk in (slice(off, off + ni * no), slice(off + ni * no, off + ni * no + no)):
+            a, b = g[blk].astype(np.float64), gr[blk]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            assert rel < 5e-3, (i, rel)
+        off += ni * no + no
+    net.close()
+
+
+def test_adam_first_step_and_training_decreases_loss(ctx, torch_mod):
+    from paper_1603_09493_amd import bpm
+    torch = torch_mod
+    th = _theta(5)
+    B = 256
+    net = bpm.Mlp(ctx, B, th)
+    rng = np.random.default_rng(6)
+    X = rng.uniform(-1, 1, (B, 12)).astype(np.float32)
+    T = np.stack([np.sin(2 * X[:, 0]) + X[:, 1], X[:, 2] * X[:, 3], (X[:, 4] > 0).astype(np.float64)], 1).astype(np.float32)
+    mask = (X[:, 5] > -0.5).astype(np.uint8)
+    Xd, Td, md = (torch.from_numpy(a).cuda() for a in (X, T, mask))
+    _case("mlp-adam", B=B)
+    lr = 1e-3
+    L0 = net.train_step(Xd, Td, md, lr)
+    th1 = net.get_params().astype(np.float64)
+    # first Adam step: theta - lr * g / (|g| + eps); compare where the oracle gradient is clearly
+    # away from zero (its sign is then the same on both sides)
+    _, gr = OM.loss_grad(th.astype(np.float64), X.astype(np.float64), T.astype(np.float64), mask)
+    big = np.abs(gr) > 1e-3 * np.abs(gr).max()
+    step = th1 - th.astype(np.float64)
+    assert np.all(np.abs(step[big] + lr * np.sign(gr[big])) <= 1e-3 * lr + 1e-6)
+    losses = [L0]
+    for _ in range(150):
+        losses.append(net.train_step(Xd, Td, md, lr))
+    assert losses[-1] < 0.5 * losses[0], (losses[0], losses[-1])
+    net.close()
+
+
+def test_sampler_bit_exact(ctx, torch_mod):
+    from oracle import oracle as O
+    from paper_1603_09493_amd import bpm
+    torch = torch_mod
+    n = 1_000_000
+    seed = (4 << 32) | 7
+    _case("sampler", n=n)
+    Xd = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    bpm.sample_designs(ctx, seed, n, Xd)
+    torch.cuda.synchronize()
+    X = Xd.cpu().numpy()
+    assert X.min() > -1.0 and X.max() < 1.0
+    rng = np.random.default_rng(8)
+    for i in np.concatenate([[0, 1, n - 1], rng.integers(0, n, 300)]):
+        i = int(i)
+        ref = []
+        for call in range(3):
+            w = O.philox4x32_10([i & 0xFFFFFFFF, i >> 32, call, 0], [seed & 0xFFFFFFFF, seed >> 32])
+            ref += [np.float32(2.0 * ((float(x) + 0.5) / 4294967296.0) - 1.0) for x in w]
+        assert np.array_equal(X[i], np.array(ref, np.float32)), i
+
+
+@pytest.mark.parametrize("n,k", [(1000, 1), (100_003, 1000), (1_000_000, 10_000), (5000, 5000)])
+def test_topk_exact(ctx, torch_mod, n, k):
+    from paper_1603_09493_amd import bpm
+    torch = torch_mod
+    rng = np.random.default_rng(n + k)
+    s = (rng.integers(-40, 40, n) / 8.0).astype(np.float32)      # many ties
+    s[rng.integers(0, n, max(1, n // 100))] = np.nan
+    s[rng.integers(0, n, max(1, n // 100))] = -np.inf
+    _case("topk", n=n, k=k)
+    net = bpm.Mlp(ctx, 16)
+    sd = torch.from_numpy(s).cuda()
+    idx = torch.empty(k, dtype=torch.int64, device="cuda")
+    net.topk(sd, k, idx)
+    torch.cuda.synchronize()
+    assert np.array_equal(idx.cpu().numpy(), OM.topk_reference(s, k))
+    net.close()
+
+
+def test_screen_round_is_consistent(ctx, torch_mod):
+    """One fused screening round: its top-k are the k best of the scores it produced, its
+    predictions are those of bpm_mlp_predict on the same designs."""
+    from paper_1603_09493_amd import bpm
+    torch = torch_mod
+    net = bpm.Mlp(ctx, 16, _theta(9))
+    n, k = 200_000, 2000
+    X = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    sc = torch.empty(n, dtype=torch.float32, device="cuda")
+    idx = torch.empty(k, dtype=torch.int64, device="cuda")
+    _case("screen", n=n, k=k)
+    net.screen(11, n, k, I.DESIGN_LO, I.DESIGN_HI, 40.0, X, Y, sc, idx)
+    Y2 = torch.empty_like(Y)
+    net.predict(X, Y2)
+    torch.cuda.synchronize()
+    assert torch.equal(Y, Y2)
+    s = sc.cpu().numpy()
+    assert np.array_equal(idx.cpu().numpy(), OM.topk_reference(s, k))
+    # the stability constraint removed some designs and kept the others' logits
+    Xn = X.cpu().numpy().astype(np.float64)
+    p = I.DESIGN_LO + (I.DESIGN_HI - I.DESIGN_LO) * 0.5 * (Xn + 1.0)
+    area = np.pi * 0.25 * p[:, 0] ** 2
+    stab = (p[:, 5] * area * p[:, 1] + p[:, 6] * area * p[:, 2]) / (1.380649e-23 * 300.0)
+    ok = stab >= 40.0
+    assert 0 < ok.sum() < n
+    assert np.all(np.isneginf(s[~ok]))
+    assert np.array_equal(s[ok], Y.cpu().numpy()[ok, 2])
+    net.close()
