@@ -76,7 +76,15 @@ typedef struct {
 int bpm_mesh_add(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, double demag_beta,
                  int32_t* mesh_id);
 
-/* Copies the group's FP64 demag operator to host memory S_out [n][n]. */
+/* As bpm_mesh_add, choosing which device copies of S to keep (flags: BPM_KEEP_S64 and/or
+ * BPM_KEEP_S32).  A group without the FP64 copy cannot run at precision 64 (and vice versa);
+ * large batches of FP32 runs keep only the FP32 copy to halve the footprint. */
+enum { BPM_KEEP_S64 = 1, BPM_KEEP_S32 = 2 };
+int bpm_mesh_add_ex(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, double demag_beta,
+                    int32_t flags, int32_t* mesh_id);
+
+/* Copies the group's demag operator to host memory S_out [n][n] (FP64, or the widened FP32 copy
+ * if only that is kept). */
 int bpm_mesh_get_S(bpm_ctx* ctx, int32_t mesh_id, double* S_out);
 
 /* Copies the host-assembled quantities of a group: V [n], rowptr [n+1], col [nnz], K [nnz],
@@ -150,6 +158,16 @@ typedef struct {
 int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);
 /* Waits for the run; returns the first ABI-level error of the run. */
 int bpm_sync(bpm_ctx* ctx);
+
+/* Autotuner of the launch shape: runs the current instances (one mesh group) for probe_attempts
+ * step attempts with each candidate number of workgroups per group cand[0..n_cand), times the
+ * stepping kernel with HIP events and keeps the fastest in *best.  ms_per_attempt (may be NULL)
+ * receives the time per attempt of each candidate (INFINITY where a candidate cannot run).  The
+ * choice is cached in the context (and appended to the file named by the environment variable
+ * BPM_TUNE_CACHE, read at bpm_create) under (size bucket of N, instance count, precision), and
+ * bpm_run uses it when wg_per_group is 0.  Results of the probe runs are discarded. */
+int bpm_autotune(bpm_ctx* ctx, const bpm_run_opts* opts, int32_t n_cand, const int32_t* cand,
+                 int64_t probe_attempts, int32_t* best, double* ms_per_attempt);
 
 /* Per-instance result.  switched: hard-layer <m_z> < 0 at the end (writing succeeded, Sec.
  * II.C).  t_sw: first time the volume-averaged hard-layer m_z reaches 0 (linear interpolation

@@ -64,9 +64,9 @@ class bpm_result(C.Structure):
 
 # every symbol declared in include/bpm_llg.h (the load test checks them all)
 SYMBOLS = [
-    "bpm_create", "bpm_destroy", "bpm_last_error", "bpm_mesh_add", "bpm_mesh_get_S",
+    "bpm_create", "bpm_destroy", "bpm_last_error", "bpm_mesh_add", "bpm_mesh_add_ex", "bpm_mesh_get_S",
     "bpm_mesh_get_assembly", "bpm_instance_add", "bpm_couple_dipoles", "bpm_clear_instances",
-    "bpm_run", "bpm_sync", "bpm_get_results", "bpm_get_trajectory", "bpm_get_m", "bpm_last_run_info",
+    "bpm_run", "bpm_sync", "bpm_autotune", "bpm_get_results", "bpm_get_trajectory", "bpm_get_m", "bpm_last_run_info",
 ]
 
 EXTRA_SYMBOLS = [
@@ -92,6 +92,7 @@ def lib():
     L.bpm_last_error.argtypes = [P]
     L.bpm_last_error.restype = C.c_char_p
     L.bpm_mesh_add.argtypes = [P, C.POINTER(bpm_mesh), P, D, C.POINTER(I32)]
+    L.bpm_mesh_add_ex.argtypes = [P, C.POINTER(bpm_mesh), P, D, I32, C.POINTER(I32)]
     L.bpm_mesh_get_S.argtypes = [P, I32, P]
     L.bpm_mesh_get_assembly.argtypes = [P, I32, C.POINTER(I32), P, P, P, P, P, P]
     L.bpm_instance_add.argtypes = [P, I32, C.POINTER(bpm_material), C.POINTER(bpm_field), P, P, C.c_uint64,
@@ -100,6 +101,7 @@ def lib():
     L.bpm_clear_instances.argtypes = [P]
     L.bpm_run.argtypes = [P, C.POINTER(bpm_run_opts), P]
     L.bpm_sync.argtypes = [P]
+    L.bpm_autotune.argtypes = [P, C.POINTER(bpm_run_opts), I32, P, I64, C.POINTER(I32), P]
     L.bpm_get_results.argtypes = [P, I32, P, P]
     L.bpm_get_trajectory.argtypes = [P, I32, P, I64, C.POINTER(I64)]
     L.bpm_get_m.argtypes = [P, I32, P]
@@ -175,7 +177,8 @@ class Context:
         return rc
 
     # meshes -------------------------------------------------------------------------------------
-    def mesh_add(self, mesh, S=None, beta=0.0) -> int:
+    def mesh_add(self, mesh, S=None, beta=0.0, keep=3) -> int:
+        """keep: 1 = FP64 demag operator only, 2 = FP32 only, 3 = both."""
         xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
         tet = np.ascontiguousarray(mesh.tet, dtype=np.int32)
         layer = np.ascontiguousarray(mesh.layer, dtype=np.int32)
@@ -184,7 +187,7 @@ class Context:
                      _p(iface) if iface.shape[0] else None)
         Sa = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
         mid = C.c_int32()
-        self._check(self.L.bpm_mesh_add(self.h, C.byref(s), _p(Sa), float(beta), C.byref(mid)))
+        self._check(self.L.bpm_mesh_add_ex(self.h, C.byref(s), _p(Sa), float(beta), int(keep), C.byref(mid)))
         self.mesh_n[mid.value] = int(xyz.shape[1])
         return mid.value
 
@@ -233,6 +236,18 @@ class Context:
         o.dt_min, o.temperature, o.max_steps = dt_min, temperature, max_steps
         o.save_every, o.traj_cap, o.wg_per_group = save_every, traj_cap, wg_per_group
         self._check(self.L.bpm_run(self.h, C.byref(o), None if stream is None else C.c_void_p(stream)))
+
+    def autotune(self, candidates, probe_attempts=60, t_end=1e-9, precision=32, integrator=DP45, rtol=1e-5,
+                 dt0=1e-15, dt_fixed=0.0):
+        o = bpm_run_opts()
+        o.precision, o.integrator, o.t_end, o.dt0, o.dt_fixed = precision, integrator, t_end, dt0, dt_fixed
+        o.rtol, o.atol, o.dt_min = rtol, rtol, 1e-19
+        cand = np.ascontiguousarray(candidates, dtype=np.int32)
+        ms = np.empty(len(cand))
+        best = C.c_int32()
+        self._check(self.L.bpm_autotune(self.h, C.byref(o), len(cand), _p(cand), int(probe_attempts),
+                                        C.byref(best), _p(ms)))
+        return best.value, ms
 
     def sync(self):
         self._check(self.L.bpm_sync(self.h))

@@ -1,6 +1,11 @@
 // C ABI of the batched FE-LLG island solver: context, mesh groups, instances, runs, results.
 // The declarations and their contracts are in include/bpm_llg.h.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -97,7 +102,16 @@ struct bpm_ctx {
   double* heun_obs = nullptr;
   long long heun_nsteps = 0;
   double heun_dt = 0.0, heun_t_end = 0.0;
+  // autotuned workgroups per mesh group, keyed by (log2 bucket of N, instances, precision)
+  std::map<std::tuple<int, int, int>, int> tune;
+  std::string tune_path;
 };
+
+static std::tuple<int, int, int> tune_key(int nmax, int rtot, int precision) {
+  int b = 0;
+  while ((1 << b) < nmax) ++b;
+  return std::make_tuple(b, rtot, precision);
+}
 
 static int fail(bpm_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -124,6 +138,12 @@ int bpm_create(bpm_ctx** out, int device) {
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;
     return BPM_EHIP;
+  }
+  if (const char* p = std::getenv("BPM_TUNE_CACHE")) {
+    c->tune_path = p;
+    std::ifstream f(p);
+    int b, r, pr, g;
+    while (f >> b >> r >> pr >> g) c->tune[std::make_tuple(b, r, pr)] = g;
   }
   *out = c;
   return BPM_OK;
@@ -184,6 +204,12 @@ static int upload_geom(bpm_ctx* c, const MeshGroup& g, DevGeom<real>& d, Arena& 
 extern "C" {
 
 int bpm_mesh_add(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double demag_beta, int32_t* mesh_id) {
+  return bpm_mesh_add_ex(c, mesh, S_host, demag_beta, BPM_KEEP_S64 | BPM_KEEP_S32, mesh_id);
+}
+
+int bpm_mesh_add_ex(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double demag_beta, int32_t flags,
+                    int32_t* mesh_id) {
+  if (c && !(flags & (BPM_KEEP_S64 | BPM_KEEP_S32))) return fail(c, BPM_EINVAL, "bpm_mesh_add_ex: keep at least one precision of S");
   if (!c) return BPM_EINVAL;
   if (!mesh || !mesh_id || !mesh->xyz || !mesh->tet || !mesh->node_layer)
     return fail(c, BPM_EINVAL, "bpm_mesh_add: null argument");
@@ -224,9 +250,15 @@ int bpm_mesh_add(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double 
     rc = demag_assemble_device(*g, beta, c->own_stream, err);
     if (rc) return fail(c, rc, "bpm_mesh_add: " + err);
   }
-  HIPCHK(c, hipMalloc(&g->dS32, sizeof(float) * (size_t)n * ldS));
-  to_float_device((size_t)n * ldS, g->dS64, g->dS32, c->own_stream);
+  if (flags & BPM_KEEP_S32) {
+    HIPCHK(c, hipMalloc(&g->dS32, sizeof(float) * (size_t)n * ldS));
+    to_float_device((size_t)n * ldS, g->dS64, g->dS32, c->own_stream);
+  }
   HIPCHK(c, hipStreamSynchronize(c->own_stream));
+  if (!(flags & BPM_KEEP_S64)) {
+    HIPCHK(c, hipFree(g->dS64));
+    g->dS64 = nullptr;
+  }
   g->S_ready = true;
   *mesh_id = (int32_t)c->meshes.size();
   c->meshes.push_back(std::move(g));
@@ -240,8 +272,15 @@ int bpm_mesh_get_S(bpm_ctx* c, int32_t id, double* S_out) {
   hipSetDevice(c->device);
   const MeshGroup& g = *c->meshes[id];
   const int ldS = (g.n + 15) / 16 * 16;
-  HIPCHK(c, hipMemcpy2D(S_out, sizeof(double) * g.n, g.dS64, sizeof(double) * ldS, sizeof(double) * g.n, g.n,
-                        hipMemcpyDeviceToHost));
+  if (g.dS64) {
+    HIPCHK(c, hipMemcpy2D(S_out, sizeof(double) * g.n, g.dS64, sizeof(double) * ldS, sizeof(double) * g.n, g.n,
+                          hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp((size_t)g.n * ldS);
+    HIPCHK(c, hipMemcpy(tmp.data(), g.dS32, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < g.n; ++k)
+      for (int l = 0; l < g.n; ++l) S_out[(size_t)k * g.n + l] = tmp[(size_t)k * ldS + l];
+  }
   return BPM_OK;
 }
 
@@ -433,8 +472,13 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   const int cap = std::max(1, per_cu * cus);
   std::vector<int> G(ng, 1);
   bool coop = false;
-  if (o->wg_per_group > 0) {
-    for (int gi = 0; gi < ng; ++gi) G[gi] = std::max(1, std::min(o->wg_per_group, c->meshes[group_ids[gi]]->n / 8));
+  int wg_req = o->wg_per_group;
+  if (wg_req <= 0 && ng == 1) {
+    auto it = c->tune.find(tune_key(nmax, ninst, (int)sizeof(real) * 8));
+    if (it != c->tune.end()) wg_req = it->second;
+  }
+  if (wg_req > 0) {
+    for (int gi = 0; gi < ng; ++gi) G[gi] = std::max(1, std::min(wg_req, c->meshes[group_ids[gi]]->n / 8));
   } else if (ng < cap) {
     // share the resident workgroups among the groups in proportion to their demag work
     std::vector<double> w(ng);
@@ -500,6 +544,7 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     v.inst0 = c->group_inst0[mi]; v.sys0 = group_sys0[gi];
     v.rowptr = d.rowptr; v.col = d.col; v.K = d.K; v.D = d.D; v.DT = d.DT;
     v.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
+    if (!v.S) return fail(c, BPM_EINVAL, "bpm_run: a mesh group does not keep S in the run precision");
     v.V = d.V; v.layer = d.layer; v.partner = d.partner; v.aif = d.aif;
     v.x = d.x; v.y = d.y; v.z = d.z;
     for (int k = 0; k < 3; ++k) v.cen[k] = g.centroid[k];
@@ -598,6 +643,7 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
     h.n = g.n; h.R = R; h.ldS = (g.n + 15) / 16 * 16; h.inst0 = (int)ic.size();
     h.rowptr = d.rowptr; h.col = d.col; h.K = d.K; h.D = d.D; h.DT = d.DT;
     h.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
+    if (!h.S) return fail(c, BPM_EINVAL, "bpm_run: a mesh group does not keep S in the run precision");
     h.V = d.V; h.layer = d.layer; h.partner = d.partner; h.aif = d.aif; h.x = d.x; h.y = d.y;
     h.Vsoft = g.vol_layer[0]; h.Vhard = g.vol_layer[1];
     const size_t cs = (size_t)g.n * R;
@@ -732,6 +778,57 @@ int bpm_run(bpm_ctx* c, const bpm_run_opts* o, void* hip_stream) {
   c->run_rfast = false;
   if (o->integrator == BPM_HEUN) return o->precision == 64 ? run_heun_typed<double>(c, o, s) : run_heun_typed<float>(c, o, s);
   return o->precision == 64 ? run_typed<double>(c, o, s) : run_typed<float>(c, o, s);
+}
+
+int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_t* cand, int64_t probe_attempts,
+                 int32_t* best, double* ms_per_attempt) {
+  if (!c) return BPM_EINVAL;
+  if (!o || n_cand <= 0 || !cand || probe_attempts <= 0 || !best)
+    return fail(c, BPM_EINVAL, "bpm_autotune: bad argument");
+  if (o->integrator == BPM_HEUN) return fail(c, BPM_EINVAL, "bpm_autotune: tunes the DP5 kernels only");
+  if (c->insts.empty()) return fail(c, BPM_ESTATE, "bpm_autotune: no instances");
+  int nmax = 1;
+  std::vector<int> meshes;
+  for (auto& I : c->insts) {
+    nmax = std::max(nmax, c->meshes[I.mesh]->n);
+    meshes.push_back(I.mesh);
+  }
+  std::sort(meshes.begin(), meshes.end());
+  meshes.erase(std::unique(meshes.begin(), meshes.end()), meshes.end());
+  if (meshes.size() != 1) return fail(c, BPM_EINVAL, "bpm_autotune: tunes runs of one mesh group");
+  double best_t = INFINITY;
+  int best_g = -1;
+  for (int q = 0; q < n_cand; ++q) {
+    bpm_run_opts p = *o;
+    p.wg_per_group = cand[q];
+    p.max_steps = probe_attempts;
+    p.traj_cap = 0;
+    int rc = bpm_run(c, &p, nullptr);
+    if (rc == BPM_OK) rc = bpm_sync(c);
+    double t = INFINITY;
+    if (rc == BPM_OK) {
+      const SysOut& so = c->h_sys_out[0];
+      const int64_t att = std::max<int64_t>(1, so.n_accept + so.n_reject);
+      t = c->kernel_ms / (double)att;
+    } else if (rc != BPM_EINVAL) {
+      return rc;
+    }
+    if (ms_per_attempt) ms_per_attempt[q] = t;
+    if (t < best_t) {
+      best_t = t;
+      best_g = c->run_G;
+    }
+  }
+  if (best_g < 0) return fail(c, BPM_EINVAL, "bpm_autotune: no candidate could run");
+  *best = best_g;
+  const auto key = tune_key(nmax, (int)c->insts.size(), o->precision);
+  c->tune[key] = best_g;
+  if (!c->tune_path.empty()) {
+    std::ofstream f(c->tune_path, std::ios::app);
+    f << std::get<0>(key) << " " << std::get<1>(key) << " " << std::get<2>(key) << " " << best_g << "\n";
+  }
+  c->have_results = false;
+  return BPM_OK;
 }
 
 int bpm_sync(bpm_ctx* c) {

@@ -15,6 +15,7 @@
 // The step decision (per system: one instance, or several dipole-coupled instances) is taken
 // redundantly by every workgroup of the group from the same reduced values.
 #include <cmath>
+#include <type_traits>
 
 #include "bpm_internal.h"
 
@@ -191,6 +192,9 @@ __device__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* 
   const int n = g.n, ldS = g.ldS;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kBlock / 64;
   constexpr int VEC = 16 / sizeof(real);
+  constexpr int U = 8;                      // vector loads per lane in flight per row chunk
+  constexpr int STEP = 64 * VEC;            // elements one wave covers per load
+  using vec_t = typename std::conditional<sizeof(real) == 4, float4, double2>::type;
   for (int rb = 0; rb < g.R; rb += RB) {
     const int rn = min(RB, g.R - rb);
     bool any = false;
@@ -207,20 +211,27 @@ __device__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* 
       real acc[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0;
-      for (int l = lane * VEC; l < ldS; l += 64 * VEC) {
-        real s[VEC];
-        if constexpr (sizeof(real) == 4) {
-          const float4 v = *reinterpret_cast<const float4*>(Srow + l);
-          s[0] = v.x; s[1] = v.y; s[2] = v.z; s[3] = v.w;
-        } else {
-          const double2 v = *reinterpret_cast<const double2*>(Srow + l);
-          s[0] = v.x; s[1] = v.y;
+      for (int l0 = lane * VEC; l0 < ldS; l0 += STEP * U) {
+        vec_t sv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int l = l0 + u * STEP;
+          if (l < ldS) sv[u] = *reinterpret_cast<const vec_t*>(Srow + l);
+          else sv[u] = vec_t{};
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if (r < rn) {
+        for (int u = 0; u < U; ++u) {
+          const int l = l0 + u * STEP;
+          if (l >= ldS) break;
+          const real* sp = reinterpret_cast<const real*>(&sv[u]);
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) acc[r] += s[q] * bL[r * ldS + l + q];
+          for (int r = 0; r < 16; ++r) {
+            if (r < rn) {
+              const vec_t bv = *reinterpret_cast<const vec_t*>(bL + r * ldS + l);
+              const real* bp = reinterpret_cast<const real*>(&bv);
+#pragma unroll
+              for (int q = 0; q < VEC; ++q) acc[r] += sp[q] * bp[q];
+            }
           }
         }
       }
@@ -462,7 +473,7 @@ __device__ void begin_attempt(const GroupView<real>& g, const RunParams& P, Ctl&
 template <typename real, bool kFixed>
 __global__ __launch_bounds__(kBlock) void dp5_kernel(const GroupView<real>* __restrict__ groups,
                                                      RunParams P, int RB) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   real* bL = reinterpret_cast<real*>(smem_raw);
   __shared__ Ctl c;
   const int2 gm = P.wg_map[blockIdx.x];
@@ -664,7 +675,7 @@ template <typename real>
 __global__ __launch_bounds__(kBlock) void energy_kernel(const GroupView<real>* __restrict__ groups,
                                                         const int2* __restrict__ inst_map, RunParams P,
                                                         double* __restrict__ energy) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   double* bL = reinterpret_cast<double*>(smem_raw);
   __shared__ double red[kBlock / 64];
   const int2 im = inst_map[blockIdx.x];   // (group, local instance)

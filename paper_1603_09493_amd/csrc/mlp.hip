@@ -131,7 +131,7 @@ __device__ __forceinline__ void fused_layer(const __bf16* __restrict__ in, __bf1
 
 __global__ __launch_bounds__(256) void mlp_predict_kernel(const float* __restrict__ X, float* __restrict__ Y, long n,
                                                           MlpDevParams P) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __bf16* act0 = reinterpret_cast<__bf16*>(smem_raw);
   __bf16* act1 = act0 + PR * PLD;
   const long r0 = (long)blockIdx.x * PR;

@@ -1,0 +1,161 @@
+"""Learned screen driver: label designs with the batched solver, train the MLP on the GPU with the
+library's own kernels, screen candidate rounds, and verify the picks with the solver.
+
+The paper's optimizer (Sec. II.A) fits a surrogate (a Gaussian process) to the evaluated designs
+and always evaluates the most promising proposal next; the solver's answer is the ground truth.
+Here the surrogate is the MLP of the C ABI and a round proposes k designs out of n candidates at
+once; the batched solver stays the judge of every pick.
+
+Design vector (12): d, t_soft, t_hard, Ms_soft, Ms_hard, K_soft, K_hard, A_int, psi, B_peak,
+alpha, t_rise -- inputs.DESIGN_LO/HI give the ranges.  Network inputs are the designs scaled to
+[-1, 1]; targets are z-scored B_sw, z-scored log t_sw and the switched flag (masked regression
+where the design did not switch).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+from . import bpm
+from . import inputs as I
+
+KB = 1.380649e-23
+
+
+def scale(x: np.ndarray) -> np.ndarray:
+    return 2.0 * (x - I.DESIGN_LO) / (I.DESIGN_HI - I.DESIGN_LO) - 1.0
+
+
+def unscale(X: np.ndarray) -> np.ndarray:
+    return I.DESIGN_LO + (I.DESIGN_HI - I.DESIGN_LO) * 0.5 * (np.asarray(X, dtype=np.float64) + 1.0)
+
+
+def stability(x: np.ndarray) -> np.ndarray:
+    """Thermal-stability proxy (K_s V_s + K_h V_h) / (kB 300 K) of design rows x."""
+    x = np.atleast_2d(x)
+    area = math.pi * 0.25 * x[:, 0] ** 2
+    return (x[:, 5] * area * x[:, 1] + x[:, 6] * area * x[:, 2]) / (KB * 300.0)
+
+
+@dataclasses.dataclass
+class Labels:
+    switched: np.ndarray   # [n] bool
+    B_sw: np.ndarray       # [n] tesla (NaN where not switched)
+    t_sw: np.ndarray       # [n] seconds (NaN where not switched)
+    status: np.ndarray     # [n] int
+    kernel_ms: float
+    wall_s: float
+
+
+def label_designs(ctx: bpm.Context, x: np.ndarray, t_end: float = 0.5e-9, precision: int = 32,
+                  mesh_seed0: int = 0, clear: bool = True) -> Labels:
+    """Runs every design (rows of x) as one island in one batched launch."""
+    if clear:
+        ctx.clear_instances()
+    ids = []
+    for q, row in enumerate(np.asarray(x, dtype=np.float64)):
+        mesh, mat, fld = I.design_inputs(row, seed=mesh_seed0 + q)
+        mid = ctx.mesh_add(mesh)
+        ids.append(ctx.instance_add(mid, mat, fld))
+    t0 = time.perf_counter()
+    ctx.run(t_end=t_end, precision=precision, rtol=1e-5 if precision == 32 else 1e-6)
+    ctx.sync()
+    wall = time.perf_counter() - t0
+    res = ctx.results(ids)
+    sw = np.array([bool(r["switched"]) for r in res])
+    tsw = np.array([r["t_sw"] for r in res])
+    bsw = np.array([r["B_sw"] for r in res])
+    st = np.array([r["status"] for r in res])
+    ok = sw & np.isfinite(tsw) & np.isfinite(bsw) & (tsw > 0)
+    return Labels(switched=ok, B_sw=np.where(ok, bsw, np.nan), t_sw=np.where(ok, tsw, np.nan), status=st,
+                  kernel_ms=ctx.last_run_info()["kernel_ms"], wall_s=wall)
+
+
+@dataclasses.dataclass
+class TargetScaler:
+    b_mu: float
+    b_sd: float
+    t_mu: float
+    t_sd: float
+
+    @staticmethod
+    def fit(lab: Labels) -> "TargetScaler":
+        b = lab.B_sw[lab.switched]
+        t = np.log(lab.t_sw[lab.switched])
+        return TargetScaler(float(b.mean()), float(b.std() + 1e-12), float(t.mean()), float(t.std() + 1e-12))
+
+    def targets(self, lab: Labels):
+        T = np.zeros((lab.switched.size, 3), np.float32)
+        m = lab.switched
+        T[m, 0] = (lab.B_sw[m] - self.b_mu) / self.b_sd
+        T[m, 1] = (np.log(lab.t_sw[m]) - self.t_mu) / self.t_sd
+        T[:, 2] = m.astype(np.float32)
+        return T, m.astype(np.uint8)
+
+    def B_of(self, y0):
+        return self.b_mu + self.b_sd * np.asarray(y0, dtype=np.float64)
+
+
+def train(net: bpm.Mlp, X: np.ndarray, T: np.ndarray, mask: np.ndarray, epochs: int = 200, batch: int = 512,
+          lr: float = 1e-3, seed: int = 0, lr_final: float = 1e-5):
+    """Minibatch Adam on device tensors (torch provides the buffers); cosine-decayed step size."""
+    import torch
+    rng = np.random.default_rng(seed)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()
+    Td = torch.from_numpy(np.ascontiguousarray(T, np.float32)).cuda()
+    md = torch.from_numpy(np.ascontiguousarray(mask, np.uint8)).cuda()
+    n = X.shape[0]
+    steps_per_epoch = max(1, n // batch)
+    total = epochs * steps_per_epoch
+    losses = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).cuda()
+        for s in range(steps_per_epoch):
+            idx = perm[s * batch:(s + 1) * batch]
+            xb, tb, mb = Xd[idx].contiguous(), Td[idx].contiguous(), md[idx].contiguous()
+            a = 0.5 * (1 + math.cos(math.pi * step / total))
+            cur = lr_final + (lr - lr_final) * a
+            want = (s == steps_per_epoch - 1)
+            L = net.train_step(xb, tb, mb, cur, batch=xb.shape[0], want_loss=want)
+            if want:
+                losses.append(L)
+            step += 1
+    return losses
+
+
+def predict(net: bpm.Mlp, X: np.ndarray) -> np.ndarray:
+    import torch
+    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()
+    Yd = torch.empty((X.shape[0], 3), dtype=torch.float32, device="cuda")
+    net.predict(Xd, Yd)
+    torch.cuda.synchronize()
+    return Yd.cpu().numpy()
+
+
+def bsw_error(net: bpm.Mlp, sc: TargetScaler, X: np.ndarray, lab: Labels):
+    """Mean and 95th percentile of |relative error| of the predicted switching field over the
+    designs that switched."""
+    Y = predict(net, X)
+    m = lab.switched
+    rel = np.abs(sc.B_of(Y[m, 0]) / lab.B_sw[m] - 1.0)
+    return float(rel.mean()), float(np.percentile(rel, 95)), Y
+
+
+def screen_round(net: bpm.Mlp, seed: int, n: int, k: int, min_stability: float):
+    """One fused screening round on the GPU; returns (picked scaled designs [k][12], seconds)."""
+    import torch
+    X = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    sc = torch.empty(n, dtype=torch.float32, device="cuda")
+    idx = torch.empty(k, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.screen(seed, n, k, I.DESIGN_LO, I.DESIGN_HI, min_stability, X, Y, sc, idx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    picks = X[idx].cpu().numpy()
+    return picks, dt, sc[idx].cpu().numpy()

@@ -1,0 +1,131 @@
+"""GPU stochastic Heun path (many realizations per island) against the oracle and against
+closed-form statistics.
+
+Bars: FP64 with the same Philox noise -- max |dm| <= 1e-9 over a short run; FP32 statistics of
+free rotational diffusion and of the Boltzmann equilibrium in a uniaxial well within their
+sampling error.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from paper_1603_09493_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.76085963023e11
+KB = 1.380649e-23
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1603_09493_amd import bpm
+    c = bpm.Context(0)
+    yield c
+    c.close()
+
+
+def _case(name, **kw):
+    print(f"[gpu-case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def test_heun_fp64_parity_with_noise(ctx, oracle_mod):
+    from paper_1603_09493_amd import bpm
+    O = oracle_mod
+    mesh, mat, fld = I.single_island_workload(n_target=300)
+    om = O.OracleMesh(mesh)
+    S = om.demag_S()
+    R = 5
+    seeds = [(3 << 32) | (100 + r) for r in range(R)]
+    T, dt, Temp = 1.0e-12, 5e-15, 300.0
+    _case("heun-fp64", n=mesh.n, R=R, steps=int(T / dt))
+    mo, ro, _ = om.run(S, [mat] * R, [fld] * R, dict(t_end=T, integrator=O.HEUN, dt_fixed=dt, temperature=Temp),
+                       seeds=seeds)
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh, S)
+    ids = [ctx.instance_add(mid, mat, fld, seed=sd) for sd in seeds]
+    ctx.run(t_end=T, precision=64, integrator=bpm.HEUN, dt_fixed=dt, temperature=Temp)
+    ctx.sync()
+    for r, i in enumerate(ids):
+        mg = ctx.get_m(i, mesh.n)
+        assert np.abs(mg - mo[r]).max() <= 1e-9, r
+    res = ctx.results(ids)
+    for a, b in zip(res, ro):
+        assert a["status"] == 0 and a["n_accept"] == b["n_accept"]
+        assert abs(a["mz_hard"] - b["mz_hard"]) < 1e-9
+    # different seeds give different paths; the noise did act
+    assert np.abs(mo[0] - mo[1]).max() > 1e-6
+
+
+def test_heun_clipped_last_step_and_graph_replay(ctx, oracle_mod):
+    """t_end not a multiple of dt: graph-replayed regular steps plus one shorter final step."""
+    from paper_1603_09493_amd import bpm
+    O = oracle_mod
+    mesh, mat, fld = I.single_island_workload(n_target=300)
+    om = O.OracleMesh(mesh)
+    S = om.demag_S()
+    T, dt = 0.2035e-12, 5e-15
+    _case("heun-clip", n=mesh.n)
+    mo, ro, _ = om.run(S, [mat], [fld], dict(t_end=T, integrator=O.HEUN, dt_fixed=dt, temperature=300.0), seeds=[9])
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh, S)
+    i = ctx.instance_add(mid, mat, fld, seed=9)
+    ctx.run(t_end=T, precision=64, integrator=bpm.HEUN, dt_fixed=dt, temperature=300.0)
+    ctx.sync()
+    assert np.abs(ctx.get_m(i, mesh.n) - mo[0]).max() <= 1e-9
+    assert ctx.results([i])[0]["n_accept"] == ro[0]["n_accept"] == 41
+
+
+def test_free_rotational_diffusion_many_realizations(ctx):
+    from paper_1603_09493_amd import bpm
+    mesh = I.island_mesh(4e-9, 4e-9, 2e-9, 3e-9, 1.0e-9, seed=2)
+    Ms, alpha, Temp = 1.0e6, 0.5, 300.0
+    mat = I.Material(Ms=(Ms, Ms), K=(0.0, 0.0), A=(0.0, 0.0), A_int=0.0, alpha=alpha)
+    fld = I.Field(kind=I.FIELD_UNIFORM, B_peak=0.0, t_rise=0.0)
+    R, t = 64, 1.0e-12
+    _case("heun-diffusion", n=mesh.n, R=R)
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh)
+    ids = [ctx.instance_add(mid, mat, fld, seed=1000 + r) for r in range(R)]
+    ctx.run(t_end=t, precision=32, integrator=bpm.HEUN, dt_fixed=1e-15, temperature=Temp)
+    ctx.sync()
+    V = ctx.mesh_get_assembly(mid)["V"]
+    mz = np.array([ctx.get_m(i, mesh.n)[2] for i in ids])
+    D = alpha * GAMMA * KB * Temp / ((1 + alpha ** 2) * Ms * V)
+    e1 = np.exp(-2 * D * t)
+    e2 = 1 / 3 + 2 / 3 * np.exp(-6 * D * t)
+    z1 = ((mz - e1) / np.sqrt(e2 - e1 ** 2)).mean() * math.sqrt(mz.size)
+    assert abs(z1) < 4.0, z1
+    assert abs((mz ** 2 - e2).mean()) < 0.01
+
+
+def _mz2_boltzmann(s):
+    Z = quad(lambda x: math.exp(s * x * x), -1, 1)[0]
+    return math.exp(s) / (s * Z) - 1 / (2 * s)
+
+
+def test_boltzmann_equilibrium_many_realizations(ctx):
+    """Independent macrospins (no exchange, no demag) in a uniaxial well at 300 K: the ensemble
+    <m_z^2> of every node matches the Boltzmann value for s = K V_i / kB T."""
+    from paper_1603_09493_amd import bpm
+    mesh = I.island_mesh(4e-9, 4e-9, 2e-9, 3e-9, 1.0e-9, seed=2)
+    Ms, K, alpha, Temp = 1.0e6, 2.0e7, 1.0, 300.0
+    mat = I.Material(Ms=(Ms, Ms), K=(K, K), A=(0.0, 0.0), A_int=0.0, alpha=alpha)
+    fld = I.Field(kind=I.FIELD_UNIFORM, B_peak=0.0, t_rise=0.0)
+    R = 256
+    _case("heun-boltzmann", n=mesh.n, R=R)
+    ctx.clear_instances()
+    S0 = np.zeros((mesh.n, mesh.n))
+    mid = ctx.mesh_add(mesh, S0)
+    ids = [ctx.instance_add(mid, mat, fld, seed=(7 << 32) | r) for r in range(R)]
+    ctx.run(t_end=60e-12, precision=32, integrator=bpm.HEUN, dt_fixed=2e-15, temperature=Temp)
+    ctx.sync()
+    V = ctx.mesh_get_assembly(mid)["V"]
+    mz = np.array([ctx.get_m(i, mesh.n)[2] for i in ids])
+    s = K * V / (KB * Temp)
+    ref = np.array([_mz2_boltzmann(x) for x in s])
+    assert abs((mz ** 2 - ref[None, :]).mean()) < 0.01
+    # both wells populated (barrier crossings happened): the sign of m_z is balanced
+    assert abs(np.sign(mz).mean()) < 0.1
