@@ -46,6 +46,95 @@ def cpu_baseline_patch(mesh, mats, flds, offs, t_sample=2e-12):
                       f"({res[0]['n_accept']} DP5 steps, {wall:.1f} s wall), rate extrapolated"}
 
 
+def surrogate_leg(n_train=448, n_test=128, t_end=0.3e-9, n_cand=1_000_000, k=10_000, epochs=300):
+    """Label designs with the batched FP32 solver, train the MLP with the library's kernels,
+    report the held-out switching-field error and time a 1M-candidate screening round."""
+    import numpy as np
+    import torch
+
+    from paper_1603_09493_amd import bpm
+    from paper_1603_09493_amd import inputs as I
+    from paper_1603_09493_amd import surrogate as SG
+    ctx = bpm.Context(0)
+    x = I.sample_designs(n_train + n_test, seed=12, fixed_alpha_rise=False)
+    lab = SG.label_designs(ctx, x, t_end=t_end)
+    solver_designs_per_s = x.shape[0] / lab.wall_s
+    X = SG.scale(x).astype(np.float32)
+    tr, te = slice(0, n_train), slice(n_train, None)
+    lab_tr = SG.Labels(lab.switched[tr], lab.B_sw[tr], lab.t_sw[tr], lab.status[tr], 0, 0)
+    lab_te = SG.Labels(lab.switched[te], lab.B_sw[te], lab.t_sw[te], lab.status[te], 0, 0)
+    sc = SG.TargetScaler.fit(lab_tr)
+    T, mask = sc.targets(lab_tr)
+    net = bpm.Mlp(ctx, 512, I.mlp_init_params(3))
+    t0 = time.perf_counter()
+    SG.train(net, X[tr], T, mask, epochs=epochs, batch=64, lr=2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    err, p95, _ = SG.bsw_error(net, sc, X[te], lab_te)
+    SG.screen_round(net, seed=1, n=n_cand, k=k, min_stability=40.0)       # warm-up
+    times = [SG.screen_round(net, seed=2 + i, n=n_cand, k=k, min_stability=40.0)[1] for i in range(3)]
+    dt = min(times)
+    net.close()
+    ctx.close()
+    return {"designs_per_s": n_cand / dt, "candidates": n_cand, "top_k": k, "screen_ms": dt * 1e3,
+            "hsw_mean_rel_err": err, "hsw_p95_rel_err": p95, "n_train": n_train, "n_test": n_test,
+            "train_s": train_s, "label_t_end_ns": t_end * 1e9,
+            "solver_designs_per_s": solver_designs_per_s,
+            "screen_vs_solver": (n_cand / dt) / solver_designs_per_s,
+            "valid_at_2pct": bool(err <= 0.02)}
+
+
+def batch_leg(n_islands=4096, t_end=1e-11, steps=1):
+    """Batched independent islands of uneven size (designs uniform in the batched ranges, N
+    proportional to volume in [300, 3000], FP32 demag only), one persistent launch, per-island
+    adaptive steps."""
+    from paper_1603_09493_amd import bpm, roofline
+    from paper_1603_09493_amd import inputs as I
+    ctx = bpm.Context(0)
+    x = I.sample_designs(n_islands, seed=2)
+    t0 = time.perf_counter()
+    sizes, nnzs, ids = [], [], []
+    for q, row in enumerate(x):
+        mesh, mat, fld = I.design_inputs(row, seed=q)
+        mid = ctx.mesh_add(mesh, keep=2)
+        ids.append(ctx.instance_add(mid, mat, fld))
+        sizes.append(mesh.n)
+        nnzs.append(int(ctx.mesh_get_assembly(mid)["rowptr"][-1]) if q < 64 else None)
+    setup_s = time.perf_counter() - t0
+    ctx.run(t_end=t_end, precision=32, rtol=1e-5)      # warm-up
+    ctx.sync()
+    _device_sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run(t_end=t_end, precision=32, rtol=1e-5)
+        ctx.sync()
+    wall = time.perf_counter() - t0
+    info = ctx.last_run_info()
+    res = ctx.results(ids)
+    att = [r["n_accept"] + r["n_reject"] for r in res]
+    nnz_per_node = sum(v for v in nnzs if v) / sum(sizes[:64])
+    by = sum(roofline.eval_bytes(n, int(n * nnz_per_node), 1, 4) * (6 * a + 1) for n, a in zip(sizes, att))
+    ctx.close()
+    return {"islands": n_islands, "simulated_ns": t_end * 1e9, "value": n_islands * t_end * 1e9 * steps / wall,
+            "unit": "island-ns/s", "setup_s": setup_s, "kernel_ms": info["kernel_ms"], "grid": info["grid"],
+            "nodes_total": int(sum(sizes)), "nodes_min": int(min(sizes)), "nodes_max": int(max(sizes)),
+            "attempts_min": int(min(att)), "attempts_max": int(max(att)),
+            "achieved_GBs": by / (info["kernel_ms"] * 1e-3) / 1e9,
+            "status_ok": int(sum(1 for r in res if r["status"] == 0))}
+
+
+def copy_calibration(mib=512, reps=3):
+    """A plain device copy of known size (for scaling the profiler's byte counters)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +144,10 @@ def main():
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--wg", type=int, default=0, help="workgroups per mesh group (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true", help="also run a 512 MiB device copy (profiling)")
+    ap.add_argument("--batch", type=int, default=0, help="also run N batched uneven islands (0 = skip)")
+    ap.add_argument("--batch-t-end", type=float, default=1e-11)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -76,9 +169,14 @@ def main():
     rtol = 1e-5 if args.precision == 32 else 1e-6
     run_kw = dict(t_end=args.t_end, precision=args.precision, rtol=rtol, wg_per_group=args.wg)
 
-    for _ in range(args.warmup):
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"patch: {len(ids)} islands x {mesh.n} nodes, setup {setup_s:.1f} s")
+    for w in range(args.warmup):
         ctx.run(**run_kw)
         ctx.sync()
+        log(f"warmup {w}: kernel {ctx.last_run_info()['kernel_ms']:.0f} ms")
     _device_sync()
     kernel_ms, attempts, wall = [], [], 0.0
     t0 = time.perf_counter()
@@ -89,6 +187,7 @@ def main():
         kernel_ms.append(info["kernel_ms"])
         r = ctx.results(ids)
         attempts.append(r[0]["n_accept"] + r[0]["n_reject"])
+        log(f"step: kernel {info['kernel_ms']:.0f} ms, {attempts[-1]} attempts")
     _device_sync()
     wall = time.perf_counter() - t0
     res = ctx.results(ids)
@@ -143,6 +242,12 @@ def main():
         },
     }
     ctx.close()
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg()
+    if args.copy_calib:
+        out["copy_calibration"] = copy_calibration()
+    if args.batch > 0:
+        out["batch"] = batch_leg(args.batch, args.batch_t_end)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_patch(mesh, mats, flds, offs)
     print(json.dumps(out), flush=True)

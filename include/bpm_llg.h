@@ -145,14 +145,19 @@ int bpm_clear_instances(bpm_ctx* ctx);
  * per component, Philox4x32-10 noise keyed by the instance seed and counter (step, node)).
  * save_every: trajectory sample every k accepted steps (0 = first and last only); traj_cap:
  * samples kept per instance.  wg_per_group: workgroups cooperating on one mesh group (0 =
- * automatic).                                                                                */
+ * automatic, or the autotuned value).  flags: see below.                                                                                */
 typedef struct {
   int32_t precision, integrator;
   double t_end, dt0, dt_fixed, rtol, atol, dt_min, temperature;
   int64_t max_steps;
   int32_t save_every, traj_cap;
-  int32_t wg_per_group, pad_;
+  int32_t wg_per_group, flags;
 } bpm_run_opts;
+
+/* bpm_run_opts.flags: BPM_FLAG_SYMMETRIC_DEMAG lets FP32 runs of groups owned by one workgroup read
+ * only the upper triangle of the symmetric demag operator (half the bytes of the dominant stream;
+ * the order of the floating-point sums then varies from run to run). */
+enum { BPM_FLAG_SYMMETRIC_DEMAG = 1 };
 
 /* Queues a run of every instance on `hip_stream` (NULL = default stream).  Asynchronous. */
 int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbpmllg.so")
 BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_ESTATE = 0, -1, -2, -3, -4
 BPM_ENONFINITE, BPM_ESTEPUNDERFLOW, BPM_EMAXSTEPS = -5, -6, -7
 FIELD_UNIFORM, FIELD_POLE = 0, 1
+FLAG_SYMMETRIC_DEMAG = 1
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
 
@@ -49,7 +50,7 @@ class bpm_run_opts(C.Structure):
                 ("dt0", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
                 ("dt_min", C.c_double), ("temperature", C.c_double), ("max_steps", C.c_int64),
                 ("save_every", C.c_int32), ("traj_cap", C.c_int32), ("wg_per_group", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 class bpm_result(C.Structure):
@@ -84,6 +85,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1603_09493_amd.build_lib")
+    # PyTorch ships its own HIP runtime under the same soname; loading it first makes this library
+    # bind to that one, so that one process holds a single HIP runtime and torch's device buffers
+    # and streams are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.bpm_create.argtypes = [C.POINTER(P), C.c_int]
@@ -229,12 +237,12 @@ class Context:
     # runs ---------------------------------------------------------------------------------------
     def run(self, t_end, precision=64, integrator=DP45, dt0=1e-15, dt_fixed=0.0, rtol=1e-6, atol=None,
             dt_min=1e-19, temperature=0.0, max_steps=0, save_every=0, traj_cap=0, wg_per_group=0,
-            stream=None):
+            flags=0, stream=None):
         o = bpm_run_opts()
         o.precision, o.integrator, o.t_end, o.dt0, o.dt_fixed = precision, integrator, t_end, dt0, dt_fixed
         o.rtol, o.atol = rtol, (rtol if atol is None else atol)
         o.dt_min, o.temperature, o.max_steps = dt_min, temperature, max_steps
-        o.save_every, o.traj_cap, o.wg_per_group = save_every, traj_cap, wg_per_group
+        o.save_every, o.traj_cap, o.wg_per_group, o.flags = save_every, traj_cap, wg_per_group, flags
         self._check(self.L.bpm_run(self.h, C.byref(o), None if stream is None else C.c_void_p(stream)))
 
     def autotune(self, candidates, probe_attempts=60, t_end=1e-9, precision=32, integrator=DP45, rtol=1e-5,

@@ -25,7 +25,7 @@ std::string hip_err_string(hipError_t e) { return hipGetErrorString(e); }
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream);
 
 template <typename real>
-hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, int, bool, bool, hipStream_t);
+hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool);
 template <typename real>
 hipError_t max_coresident(int, int, bool, int*, int*);
 template <typename real>
@@ -459,14 +459,15 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     nmax = std::max(nmax, g.n);
     Rmax = std::max(Rmax, (int)by_mesh[group_ids[gi]].size());
   }
-  const size_t lds_budget = 96 * 1024;
+  const bool sym = (o->flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4;
+  const size_t lds_budget = sym ? 48 * 1024 : 96 * 1024;
   int RB = (int)std::max<size_t>(1, std::min<size_t>(16, lds_budget / (sizeof(real) * (size_t)ldS_max)));
   RB = std::min(RB, Rmax);
   if ((size_t)RB * ldS_max * sizeof(real) > 120 * 1024)
     return fail(c, BPM_EINVAL, "bpm_run: island too large for the LDS staging of the demag product");
   int per_cu = 0, cus = 0;
   {
-    hipError_t e = max_coresident<real>(RB, ldS_max, fixed, &per_cu, &cus);
+    hipError_t e = max_coresident<real>(sym ? 2 * RB : RB, ldS_max, fixed, &per_cu, &cus);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
   }
   const int cap = std::max(1, per_cu * cus);
@@ -586,12 +587,13 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   P.t_end = o->t_end; P.dt0 = o->dt0; P.dt_fixed = o->dt_fixed; P.rtol = o->rtol; P.atol = o->atol;
   P.dt_min = o->dt_min; P.temperature = o->temperature; P.max_steps = o->max_steps;
   P.save_every = o->save_every; P.traj_cap = tcap;
+  P.flags = o->flags;
   P.inst = d_ic; P.sys = d_sys; P.sys_out = c->d_sys_out; P.inst_out = c->d_inst_out; P.traj = c->d_traj;
   P.err_acc = d_err; P.obs_acc = d_obs; P.mom_acc = d_mom; P.wg_map = d_map;
 
   HIPCHK(c, hipEventRecord(c->ev0, stream));
   {
-    hipError_t e = launch_dp5<real>(d_groups, P, grid, RB, ldS_max, fixed, coop, stream);
+    hipError_t e = launch_dp5<real>(d_groups, P, grid, RB, ldS_max, fixed, coop, stream, sym);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("stepping kernel launch: ") + hipGetErrorString(e));
   }
   HIPCHK(c, hipEventRecord(c->ev1, stream));

@@ -127,6 +127,7 @@ struct RunParams {
   double t_end, dt0, dt_fixed, rtol, atol, dt_min, temperature;
   int64_t max_steps;
   int32_t save_every, traj_cap;
+  int32_t flags, pad_;
   const InstConst* inst;
   const SysView* sys;
   SysOut* sys_out;

@@ -11,7 +11,7 @@
 //
 // Layout: per mesh group the state is [3][N][R] (realization fastest), so the charges of all
 // realizations form an N x R matrix B and the demag potentials U = S B are one dense GEMM per
-// group on the matrix cores (v_mfma_f32_16x16x4f32 for FP32, v_mfma_f64_16x16x4f64 for FP64).
+// group, on the matrix cores for FP32 (v_mfma_f32_16x16x4f32) and with FP64 FMA tiles for FP64.
 // Three launches per field evaluation (SpMM A, GEMM B, pointwise C); the step counter lives in
 // device memory so one step is a replayable HIP graph.
 #include <cmath>
@@ -99,18 +99,12 @@ __global__ __launch_bounds__(256) void heun_phase_A(const HeunGroup<real>* __res
 // each wave a 32 x 32 quarter = 2 x 2 tiles of 16 x 16; K staged through LDS 16 at a time
 // ---------------------------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ doublex4 mfma4(double a, double b, doublex4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
+// FP32: matrix cores.  Lane layout of v_mfma_f32_16x16x4f32 (wave64): lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; the accumulator lane l holds C[4 (l / 16) + i][l % 16].
+// FP64: the same tiling with each lane owning a 4 x 4 block of its wave's 32 x 32 quarter (FMA).
 template <typename real>
 __global__ __launch_bounds__(256) void heun_phase_B(const HeunGroup<real>* __restrict__ G, const int4* __restrict__ tmap) {
-  typedef typename std::conditional<sizeof(real) == 4, floatx4, doublex4>::type accx4;
   constexpr int TM = 64, TN = 64, TK = 16;
   __shared__ real As[TK][TM + 4];   // As[k][m]
   __shared__ real Bs[TK][TN + 4];   // Bs[k][n]
@@ -120,10 +114,15 @@ __global__ __launch_bounds__(256) void heun_phase_B(const HeunGroup<real>* __res
   const int m0 = tm.y, n0 = tm.z;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;
-  accx4 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int i = 0; i < 4; ++i) acc[a][b][i] = 0;
+  floatx4 acc[2][2];
+  double accd[4][4];
+  if constexpr (sizeof(real) == 4) {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  } else {
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) accd[a][b] = 0.0;
+  }
   for (int k0 = 0; k0 < n; k0 += TK) {
     __syncthreads();
     for (int idx = tid; idx < TM * TK; idx += 256) {
@@ -137,24 +136,45 @@ __global__ __launch_bounds__(256) void heun_phase_B(const HeunGroup<real>* __res
       Bs[kk][nn] = (k < n && col < R) ? g.b[(size_t)k * R + col] : (real)0;
     }
     __syncthreads();
+    if constexpr (sizeof(real) == 4) {
 #pragma unroll
-    for (int ks = 0; ks < TK; ks += 4) {
-      real af[2], bfr[2];
-      for (int t = 0; t < 2; ++t) {
-        af[t] = As[ks + (lane >> 4)][wr + 16 * t + (lane & 15)];
-        bfr[t] = Bs[ks + (lane >> 4)][wc + 16 * t + (lane & 15)];
+      for (int ks = 0; ks < TK; ks += 4) {
+        float af[2], bfr[2];
+        for (int t = 0; t < 2; ++t) {
+          af[t] = As[ks + (lane >> 4)][wr + 16 * t + (lane & 15)];
+          bfr[t] = Bs[ks + (lane >> 4)][wc + 16 * t + (lane & 15)];
+        }
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bfr[b], acc[a][b], 0, 0, 0);
       }
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma4(af[a], bfr[b], acc[a][b]);
+    } else {
+      const int r4 = wr + 4 * (lane >> 3), c4 = wc + 4 * (lane & 7);
+#pragma unroll 4
+      for (int kk = 0; kk < TK; ++kk) {
+        double av[4], bv[4];
+        for (int a = 0; a < 4; ++a) av[a] = (double)As[kk][r4 + a];
+        for (int b = 0; b < 4; ++b) bv[b] = (double)Bs[kk][c4 + b];
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b) accd[a][b] += av[a] * bv[b];
+      }
     }
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int i = 0; i < 4; ++i) {
-        const int row = m0 + wr + 16 * a + 4 * (lane >> 4) + i;
-        const int col = n0 + wc + 16 * b + (lane & 15);
-        if (row < n && col < R) g.u[(size_t)row * R + col] = acc[a][b][i];
+  if constexpr (sizeof(real) == 4) {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < 4; ++i) {
+          const int row = m0 + wr + 16 * a + 4 * (lane >> 4) + i;
+          const int col = n0 + wc + 16 * b + (lane & 15);
+          if (row < n && col < R) g.u[(size_t)row * R + col] = acc[a][b][i];
+        }
+  } else {
+    const int r4 = wr + 4 * (lane >> 3), c4 = wc + 4 * (lane & 7);
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        const int row = m0 + r4 + a, col = n0 + c4 + b;
+        if (row < n && col < R) g.u[(size_t)row * R + col] = (real)accd[a][b];
       }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -246,6 +246,83 @@ __device__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* 
   }
 }
 
+// Symmetric variant for a group owned by one workgroup: only the upper triangle of S is read.
+// Row k contributes S_kl b_l (l >= k) to u_k through the wave reduction and S_kl b_k (l > k) to u_l
+// through LDS atomics; uL (RB x ldS in LDS, after bL) collects u.  The summation order depends on
+// the atomics' order, so this variant is used for FP32 runs only.
+template <typename real>
+__device__ void phase_B_sym(const GroupView<real>& g, Ctl& c, real* bL, int RB) {
+  const int n = g.n, ldS = g.ldS;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kBlock / 64;
+  constexpr int VEC = 16 / sizeof(real);
+  constexpr int U = 4;
+  constexpr int STEP = 64 * VEC;
+  using vec_t = typename std::conditional<sizeof(real) == 4, float4, double2>::type;
+  real* uL = bL + (size_t)RB * ldS;
+  for (int rb = 0; rb < g.R; rb += RB) {
+    const int rn = min(RB, g.R - rb);
+    bool any = false;
+    for (int r = rb; r < rb + rn; ++r) any = any || c.active[c.isys[r]];
+    if (!any) continue;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rn * ldS; idx += kBlock) {
+      const int r = idx / ldS, l = idx - r * ldS;
+      bL[idx] = l < n ? g.b[(size_t)(rb + r) * n + l] : (real)0;
+      uL[idx] = (real)0;
+    }
+    __syncthreads();
+    for (int k = wid; k < n; k += nw) {
+      const real* Srow = g.S + (size_t)k * ldS;
+      real acc[16], bk[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        acc[r] = 0;
+        bk[r] = r < rn ? bL[r * ldS + k] : (real)0;
+      }
+      const int start = k & ~(VEC - 1);
+      for (int l0 = start + lane * VEC; l0 < ldS; l0 += STEP * U) {
+        vec_t sv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int l = l0 + u * STEP;
+          if (l < ldS) sv[u] = *reinterpret_cast<const vec_t*>(Srow + l);
+          else sv[u] = vec_t{};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int l = l0 + u * STEP;
+          if (l >= ldS) break;
+          const real* sp = reinterpret_cast<const real*>(&sv[u]);
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            const int col = l + q;
+            if (col < k || col >= n) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              if (r < rn) {
+                acc[r] += sp[q] * bL[r * ldS + col];
+                if (col > k) atomicAdd(&uL[r * ldS + col], sp[q] * bk[r]);
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (r < rn) {
+          const real v = wave_sum(acc[r]);
+          if (lane == 0) atomicAdd(&uL[r * ldS + k], v);
+        }
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rn * n; idx += kBlock) {
+      const int r = idx / n, l = idx - r * n;
+      g.u[(size_t)(rb + r) * n + l] = uL[r * ldS + l];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // phase C: effective field, LLG right-hand side, next stage input, reductions
 // ---------------------------------------------------------------------------------------------
@@ -404,7 +481,8 @@ __device__ void field_eval(const GroupView<real>& g, const RunParams& P, Ctl& c,
                            real* bL, int RB) {
   phase_A<real>(g, P, c, i0, i1, ysrc, ev);
   group_sync(gs);
-  phase_B<real>(g, c, i0, i1, bL, RB);
+  if (g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real>(g, c, bL, RB);
+  else phase_B<real>(g, c, i0, i1, bL, RB);
   group_sync(gs);
   phase_C<real, kFixed>(g, P, c, i0, i1, s, ysrc, ydst, it, ev);
   group_sync(gs);
@@ -720,7 +798,35 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(const GroupView<real>* _
     if (lane == 0) ed += 0.5 * kMu0 * bL[k] * acc;
   }
   e_loc += ed;
-  const double tot = block_sum(e_loc, red);
+  double tot = block_sum(e_loc, red);
+  // point-dipole energy of a coupled island: -1/2 mu_J . B_dip,J (half of each pair energy)
+  const SysView sv = P.sys[ic.sys];
+  if (sv.coupled && sv.count > 1) {
+    double muJ[3] = {0, 0, 0}, Bd[3] = {0, 0, 0};
+    for (int I = sv.inst0; I < sv.inst0 + sv.count; ++I) {
+      const InstConst& ci = P.inst[I];
+      const real* mI = g.m + (size_t)(I - g.inst0) * 3 * n;
+      double mu[3];
+      for (int d = 0; d < 3; ++d) {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < n; i += kBlock) a += ci.Ms[g.layer[i]] * (double)g.V[i] * (double)mI[d * n + i];
+        mu[d] = block_sum(a, red);
+      }
+      if (I == g.inst0 + r) {
+        muJ[0] = mu[0]; muJ[1] = mu[1]; muJ[2] = mu[2];
+        continue;
+      }
+      const double d0 = ic.off[0] - ci.off[0], d1 = ic.off[1] - ci.off[1], d2 = ic.off[2] - ci.off[2];
+      const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double e0 = d0 / rr, e1 = d1 / rr, e2 = d2 / rr;
+      const double mr = mu[0] * e0 + mu[1] * e1 + mu[2] * e2;
+      const double f = kMu0 / (4.0 * kPi * rr * rr * rr);
+      Bd[0] += f * (3.0 * mr * e0 - mu[0]);
+      Bd[1] += f * (3.0 * mr * e1 - mu[1]);
+      Bd[2] += f * (3.0 * mr * e2 - mu[2]);
+    }
+    tot += -0.5 * (muJ[0] * Bd[0] + muJ[1] * Bd[1] + muJ[2] * Bd[2]);
+  }
   if (threadIdx.x == 0) energy[g.inst0 + r] = tot;
 }
 
@@ -729,8 +835,8 @@ __global__ __launch_bounds__(kBlock) void energy_kernel(const GroupView<real>* _
 // ---------------------------------------------------------------------------------------------
 template <typename real>
 hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int grid, int RB,
-                      int ldS_max, bool fixed, bool cooperative, hipStream_t stream) {
-  const size_t shm = (size_t)RB * ldS_max * sizeof(real);
+                      int ldS_max, bool fixed, bool cooperative, hipStream_t stream, bool sym) {
+  const size_t shm = (size_t)(sym ? 2 : 1) * RB * ldS_max * sizeof(real);
   void* args[] = {(void*)&d_groups, (void*)&P, (void*)&RB};
   const void* fn = fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true>)
                          : reinterpret_cast<const void*>(&dp5_kernel<real, false>);
@@ -767,8 +873,8 @@ hipError_t launch_energy(const GroupView<real>* d_groups, const int2* d_inst_map
   return hipGetLastError();
 }
 
-template hipError_t launch_dp5<float>(const GroupView<float>*, const RunParams&, int, int, int, bool, bool, hipStream_t);
-template hipError_t launch_dp5<double>(const GroupView<double>*, const RunParams&, int, int, int, bool, bool, hipStream_t);
+template hipError_t launch_dp5<float>(const GroupView<float>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool);
+template hipError_t launch_dp5<double>(const GroupView<double>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool);
 template hipError_t max_coresident<float>(int, int, bool, int*, int*);
 template hipError_t max_coresident<double>(int, int, bool, int*, int*);
 template hipError_t launch_energy<float>(const GroupView<float>*, const int2*, int, const RunParams&, double*, int, int, hipStream_t);
