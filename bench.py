@@ -173,8 +173,13 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     log(f"patch: {len(ids)} islands x {mesh.n} nodes, setup {setup_s:.1f} s")
+    tuned = None
+    if args.wg == 0:
+        cands = [16, 32, 48, 64, 96, 128, 192, 256]
+        tuned, ms = ctx.autotune(cands, probe_attempts=80, t_end=args.t_end, precision=args.precision, rtol=rtol)
+        log("autotune (us/attempt): " + ", ".join(f"{c}:{1e3*m:.0f}" for c, m in zip(cands, ms)) + f" -> {tuned}")
     for w in range(args.warmup):
-        ctx.run(**run_kw)
+        ctx.run(**dict(run_kw, t_end=args.t_end / 10))     # warm-up: same launch, shorter window
         ctx.sync()
         log(f"warmup {w}: kernel {ctx.last_run_info()['kernel_ms']:.0f} ms")
     _device_sync()
@@ -222,6 +227,7 @@ def main():
             "nnz": nnz,
             "simulated_ns": args.t_end * 1e9,
             "wg_per_group": ctx.last_run_info()["wg_per_group"],
+            "autotuned_wg_per_group": tuned,
             "grid": ctx.last_run_info()["grid"],
             "attempts": attempts[-1],
             "n_reject": res[0]["n_reject"],

@@ -157,7 +157,8 @@ typedef struct {
 /* bpm_run_opts.flags: BPM_FLAG_SYMMETRIC_DEMAG lets FP32 runs of groups owned by one workgroup read
  * only the upper triangle of the symmetric demag operator (half the bytes of the dominant stream;
  * the order of the floating-point sums then varies from run to run). */
-enum { BPM_FLAG_SYMMETRIC_DEMAG = 1 };
+enum { BPM_FLAG_SYMMETRIC_DEMAG = 1,
+       BPM_FLAG_WG1024 = 2   /* 1024-thread workgroups for the stepping kernel (default 256) */ };
 
 /* Queues a run of every instance on `hip_stream` (NULL = default stream).  Asynchronous. */
 int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);
@@ -165,7 +166,8 @@ int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);
 int bpm_sync(bpm_ctx* ctx);
 
 /* Autotuner of the launch shape: runs the current instances (one mesh group) for probe_attempts
- * step attempts with each candidate number of workgroups per group cand[0..n_cand), times the
+ * step attempts with each candidate number of workgroups per group cand[0..n_cand) (a negative
+ * candidate -g means g workgroups of 1024 threads instead of 256), times the
  * stepping kernel with HIP events and keeps the fastest in *best.  ms_per_attempt (may be NULL)
  * receives the time per attempt of each candidate (INFINITY where a candidate cannot run).  The
  * choice is cached in the context (and appended to the file named by the environment variable
@@ -227,7 +229,7 @@ int bpm_mlp_grads(bpm_mlp* net, const float* X, const float* T, const uint8_t* m
  * receives the loss before the step (this synchronises the stream). */
 int bpm_mlp_train_step(bpm_mlp* net, const float* X, const float* T, const uint8_t* mask,
                        int32_t batch, float lr, float* loss, void* hip_stream);
-/* n candidate designs, scaled features X [n][12] in (-1, 1): X[i][f] = 2u - 1, u = (w + 1/2) 2^-32,
+/* n candidate designs, scaled features X [n][12] in [-1, 1]: X[i][f] = 2u - 1 (rounded to FP32), u = (w + 1/2) 2^-32,
  * w the words of Philox4x32-10 with key (seed low, seed high) and counter (i low, i high, f/4, 0). */
 int bpm_sample_designs(bpm_ctx* ctx, uint64_t seed, int64_t n, float* X, void* hip_stream);
 /* Indices of the k largest scores, ordered by (score descending, index ascending); NaN ranks

@@ -19,6 +19,7 @@ BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_ESTATE = 0, -1, -2, -3, -4
 BPM_ENONFINITE, BPM_ESTEPUNDERFLOW, BPM_EMAXSTEPS = -5, -6, -7
 FIELD_UNIFORM, FIELD_POLE = 0, 1
 FLAG_SYMMETRIC_DEMAG = 1
+FLAG_WG1024 = 2
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
 

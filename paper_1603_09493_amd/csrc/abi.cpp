@@ -25,9 +25,9 @@ std::string hip_err_string(hipError_t e) { return hipGetErrorString(e); }
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream);
 
 template <typename real>
-hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool);
+hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool, int, int);
 template <typename real>
-hipError_t max_coresident(int, int, bool, int*, int*);
+hipError_t max_coresident(int, int, bool, int, int, int*, int*);
 template <typename real>
 hipError_t launch_energy(const GroupView<real>*, const int2*, int, const RunParams&, double*, int, int, hipStream_t);
 
@@ -81,6 +81,7 @@ struct bpm_ctx {
   int run_precision = 64, run_traj_cap = 0, run_grid = 0, run_G = 0;
   int run_ninst = 0, run_nsys = 0;
   bool run_rfast = false;                  // state layout [3][N][R] (Heun path)
+  int run_csr_cap = 0;                     // CSR entries staged in LDS per workgroup (0 = none)
   std::vector<int32_t> slot_R;             // run slot -> R of its group (Heun path)
   hipGraphExec_t graph_exec = nullptr;
   std::vector<int32_t> inst_order;         // run slot -> instance id
@@ -460,6 +461,12 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     Rmax = std::max(Rmax, (int)by_mesh[group_ids[gi]].size());
   }
   const bool sym = (o->flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4;
+  int tuned_wg = 0;
+  if (o->wg_per_group <= 0 && ng == 1) {
+    auto it = c->tune.find(tune_key(nmax, ninst, (int)sizeof(real) * 8));
+    if (it != c->tune.end()) tuned_wg = it->second;
+  }
+  const int bs = ((o->flags & BPM_FLAG_WG1024) || tuned_wg < 0) ? 1024 : 256;
   const size_t lds_budget = sym ? 48 * 1024 : 96 * 1024;
   int RB = (int)std::max<size_t>(1, std::min<size_t>(16, lds_budget / (sizeof(real) * (size_t)ldS_max)));
   RB = std::min(RB, Rmax);
@@ -467,17 +474,13 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     return fail(c, BPM_EINVAL, "bpm_run: island too large for the LDS staging of the demag product");
   int per_cu = 0, cus = 0;
   {
-    hipError_t e = max_coresident<real>(sym ? 2 * RB : RB, ldS_max, fixed, &per_cu, &cus);
+    hipError_t e = max_coresident<real>(sym ? 2 * RB : RB, ldS_max, fixed, bs, 0, &per_cu, &cus);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
   }
   const int cap = std::max(1, per_cu * cus);
   std::vector<int> G(ng, 1);
   bool coop = false;
-  int wg_req = o->wg_per_group;
-  if (wg_req <= 0 && ng == 1) {
-    auto it = c->tune.find(tune_key(nmax, ninst, (int)sizeof(real) * 8));
-    if (it != c->tune.end()) wg_req = it->second;
-  }
+  int wg_req = o->wg_per_group > 0 ? o->wg_per_group : (tuned_wg < 0 ? -tuned_wg : tuned_wg);
   if (wg_req > 0) {
     for (int gi = 0; gi < ng; ++gi) G[gi] = std::max(1, std::min(wg_req, c->meshes[group_ids[gi]]->n / 8));
   } else if (ng < cap) {
@@ -500,6 +503,27 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     if (G[gi] > 1) coop = true;
   }
   if (coop && grid > cap) return fail(c, BPM_EINVAL, "bpm_run: workgroups per group exceed the resident capacity");
+  // stage the owned CSR rows in LDS for cooperative runs when the extra LDS keeps every
+  // workgroup resident
+  int csr_cap = 0;
+  if (coop) {
+    int own_max = 0;
+    for (int gi = 0; gi < ng; ++gi) {
+      const MeshGroup& g = *c->meshes[group_ids[gi]];
+      for (int w = 0; w < G[gi]; ++w) {
+        const int a = (int)((long long)g.n * w / G[gi]), b = (int)((long long)g.n * (w + 1) / G[gi]);
+        own_max = std::max(own_max, g.rowptr[b] - g.rowptr[a]);
+      }
+    }
+    const int want = own_max + 64;
+    if ((size_t)want * (7 * sizeof(real) + 8) <= 40 * 1024) {
+      int pc2 = 0, cu2 = 0;
+      if (max_coresident<real>(sym ? 2 * RB : RB, ldS_max, fixed, bs, want, &pc2, &cu2) == hipSuccess &&
+          pc2 * cu2 >= grid)
+        csr_cap = want;
+    }
+  }
+  c->run_csr_cap = csr_cap;
   c->run_grid = grid;
   c->run_G = *std::max_element(G.begin(), G.end());
 
@@ -593,7 +617,7 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
 
   HIPCHK(c, hipEventRecord(c->ev0, stream));
   {
-    hipError_t e = launch_dp5<real>(d_groups, P, grid, RB, ldS_max, fixed, coop, stream, sym);
+    hipError_t e = launch_dp5<real>(d_groups, P, grid, RB, ldS_max, fixed, coop, stream, sym, bs, csr_cap);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("stepping kernel launch: ") + hipGetErrorString(e));
   }
   HIPCHK(c, hipEventRecord(c->ev1, stream));
@@ -802,7 +826,8 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
   int best_g = -1;
   for (int q = 0; q < n_cand; ++q) {
     bpm_run_opts p = *o;
-    p.wg_per_group = cand[q];
+    p.wg_per_group = cand[q] > 0 ? cand[q] : -cand[q];
+    p.flags = cand[q] > 0 ? (o->flags & ~BPM_FLAG_WG1024) : (o->flags | BPM_FLAG_WG1024);
     p.max_steps = probe_attempts;
     p.traj_cap = 0;
     int rc = bpm_run(c, &p, nullptr);
@@ -818,7 +843,7 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
     if (ms_per_attempt) ms_per_attempt[q] = t;
     if (t < best_t) {
       best_t = t;
-      best_g = c->run_G;
+      best_g = cand[q] > 0 ? c->run_G : -c->run_G;
     }
   }
   if (best_g < 0) return fail(c, BPM_EINVAL, "bpm_autotune: no candidate could run");

@@ -236,3 +236,21 @@ def test_bad_arguments_are_rejected(ctx, cfg0):
     broken.tet[0, 0] = mesh.n + 5
     with pytest.raises(bpm.BpmError):
         ctx.mesh_add(broken, None)
+
+
+def test_symmetric_demag_product_matches_full(ctx, cfg0, oracle_mod):
+    """FP32 with the upper-triangle demag product (one workgroup per group) against the full
+    product and the FP64 oracle."""
+    from paper_1603_09493_amd import bpm
+    mesh, mat, fld, om, S = cfg0
+    fl = dataclasses.replace(fld, B_peak=1.8)
+    T = 0.2e-9
+    _print_case("fp32-symmetric", n=mesh.n)
+    mo, ro, _ = om.run(S, [mat], [fl], dict(t_end=T, rtol=1e-6))
+    m_full, r_full, _ = _run_gpu(ctx, mesh, S, [mat], [fl], t_end=T, precision=32, rtol=1e-5, wg_per_group=1)
+    m_sym, r_sym, _ = _run_gpu(ctx, mesh, S, [mat], [fl], t_end=T, precision=32, rtol=1e-5, wg_per_group=1,
+                               flags=bpm.FLAG_SYMMETRIC_DEMAG)
+    assert r_sym[0]["switched"] and r_full[0]["switched"]
+    assert abs(r_sym[0]["t_sw"] / ro[0]["t_sw"] - 1) <= 0.01
+    assert abs(r_sym[0]["B_sw"] / ro[0]["B_sw"] - 1) <= 0.01
+    assert abs(r_sym[0]["t_sw"] / r_full[0]["t_sw"] - 1) <= 1e-3
