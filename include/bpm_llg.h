@@ -156,9 +156,12 @@ typedef struct {
 
 /* bpm_run_opts.flags: BPM_FLAG_SYMMETRIC_DEMAG lets FP32 runs of groups owned by one workgroup read
  * only the upper triangle of the symmetric demag operator (half the bytes of the dominant stream;
- * the order of the floating-point sums then varies from run to run). */
+ * the order of the floating-point sums then varies from run to run).  Runs whose groups span
+ * several workgroups keep each workgroup's rows of S in LDS for the whole launch when they fit
+ * (the demag product then reads no S from HBM); BPM_FLAG_STREAM_S turns that off. */
 enum { BPM_FLAG_SYMMETRIC_DEMAG = 1,
-       BPM_FLAG_WG1024 = 2   /* 1024-thread workgroups for the stepping kernel (default 256) */ };
+       BPM_FLAG_WG512 = 2,    /* 512-thread workgroups for the stepping kernel (default 256) */
+       BPM_FLAG_STREAM_S = 4  /* stream S from global memory even where its rows fit in LDS */ };
 
 /* Queues a run of every instance on `hip_stream` (NULL = default stream).  Asynchronous. */
 int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);
@@ -167,7 +170,7 @@ int bpm_sync(bpm_ctx* ctx);
 
 /* Autotuner of the launch shape: runs the current instances (one mesh group) for probe_attempts
  * step attempts with each candidate number of workgroups per group cand[0..n_cand) (a negative
- * candidate -g means g workgroups of 1024 threads instead of 256), times the
+ * candidate -g means g workgroups of 512 threads instead of 256), times the
  * stepping kernel with HIP events and keeps the fastest in *best.  ms_per_attempt (may be NULL)
  * receives the time per attempt of each candidate (INFINITY where a candidate cannot run).  The
  * choice is cached in the context (and appended to the file named by the environment variable
@@ -195,6 +198,11 @@ int bpm_get_trajectory(bpm_ctx* ctx, int32_t id, double* out, int64_t cap, int64
 int bpm_get_m(bpm_ctx* ctx, int32_t id, double* m_out);
 /* Wall time of the last run's kernels (ms, HIP events on the run stream) and launch data. */
 int bpm_last_run_info(bpm_ctx* ctx, double* kernel_ms, int32_t* grid, int32_t* wg_per_group);
+/* Launch layout of the last DP5 run (any pointer may be NULL): threads per workgroup, rows of S
+ * kept in LDS per workgroup (0 = S streamed), CSR entries staged in LDS (0 = none), instances per
+ * staged block of the demag right-hand sides, and dynamic LDS bytes per workgroup. */
+int bpm_last_run_layout(bpm_ctx* ctx, int32_t* threads_per_wg, int32_t* s_rows_lds, int32_t* csr_cap_lds,
+                        int32_t* rhs_block, int64_t* lds_bytes);
 
 
 /* ------------------------------------------------------------------------------------------ */

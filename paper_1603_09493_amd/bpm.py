@@ -19,7 +19,8 @@ BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_ESTATE = 0, -1, -2, -3, -4
 BPM_ENONFINITE, BPM_ESTEPUNDERFLOW, BPM_EMAXSTEPS = -5, -6, -7
 FIELD_UNIFORM, FIELD_POLE = 0, 1
 FLAG_SYMMETRIC_DEMAG = 1
-FLAG_WG1024 = 2
+FLAG_WG512 = 2
+FLAG_STREAM_S = 4
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
 
@@ -69,6 +70,7 @@ SYMBOLS = [
     "bpm_create", "bpm_destroy", "bpm_last_error", "bpm_mesh_add", "bpm_mesh_add_ex", "bpm_mesh_get_S",
     "bpm_mesh_get_assembly", "bpm_instance_add", "bpm_couple_dipoles", "bpm_clear_instances",
     "bpm_run", "bpm_sync", "bpm_autotune", "bpm_get_results", "bpm_get_trajectory", "bpm_get_m", "bpm_last_run_info",
+    "bpm_last_run_layout",
 ]
 
 EXTRA_SYMBOLS = [
@@ -115,6 +117,7 @@ def lib():
     L.bpm_get_trajectory.argtypes = [P, I32, P, I64, C.POINTER(I64)]
     L.bpm_get_m.argtypes = [P, I32, P]
     L.bpm_last_run_info.argtypes = [P, C.POINTER(D), C.POINTER(I32), C.POINTER(I32)]
+    L.bpm_last_run_layout.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]
     L.bpm_mlp_num_params.argtypes = []
     L.bpm_mlp_create.argtypes = [P, I32, P, C.POINTER(P)]
     L.bpm_mlp_destroy.argtypes = [P]
@@ -282,6 +285,15 @@ class Context:
         ms = C.c_double(); grid = C.c_int32(); G = C.c_int32()
         self._check(self.L.bpm_last_run_info(self.h, C.byref(ms), C.byref(grid), C.byref(G)))
         return dict(kernel_ms=ms.value, grid=grid.value, wg_per_group=G.value)
+
+    def last_run_layout(self):
+        """Threads per workgroup, rows of S kept in LDS (0 = streamed), CSR entries staged in LDS,
+        instances per staged right-hand-side block and dynamic LDS bytes of the last DP5 run."""
+        v = [C.c_int32() for _ in range(4)]
+        b = C.c_int64()
+        self._check(self.L.bpm_last_run_layout(self.h, *(C.byref(x) for x in v), C.byref(b)))
+        return dict(threads=v[0].value, s_rows_lds=v[1].value, csr_cap=v[2].value, rhs_block=v[3].value,
+                    lds_bytes=b.value)
 
 
 def _dp(x):

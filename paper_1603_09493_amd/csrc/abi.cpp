@@ -25,16 +25,18 @@ std::string hip_err_string(hipError_t e) { return hipGetErrorString(e); }
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream);
 
 template <typename real>
-hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool, int, int);
+size_t dp5_lds_bytes(const LdsPlan&);
 template <typename real>
-hipError_t max_coresident(int, int, bool, int, int, int*, int*);
+hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, const LdsPlan&, bool, bool, hipStream_t, int);
 template <typename real>
-hipError_t launch_energy(const GroupView<real>*, const int2*, int, const RunParams&, double*, int, int, hipStream_t);
+hipError_t max_coresident(const LdsPlan&, bool, int, int*, int*);
+template <typename real>
+hipError_t launch_energy(const GroupView<real>*, const int2*, int, const RunParams&, double*, int, hipStream_t);
 
 // device copies of the assembled quantities, in one precision
 template <typename real>
 struct DevGeom {
-  int32_t *rowptr = nullptr, *col = nullptr, *layer = nullptr, *partner = nullptr;
+  int32_t *rowptr = nullptr, *col = nullptr, *colx = nullptr, *layer = nullptr, *partner = nullptr;
   real *K = nullptr, *D = nullptr, *DT = nullptr, *V = nullptr, *aif = nullptr;
   double *x = nullptr, *y = nullptr, *z = nullptr;
 };
@@ -82,6 +84,8 @@ struct bpm_ctx {
   int run_ninst = 0, run_nsys = 0;
   bool run_rfast = false;                  // state layout [3][N][R] (Heun path)
   int run_csr_cap = 0;                     // CSR entries staged in LDS per workgroup (0 = none)
+  LdsPlan run_plan{};                      // LDS plan of the last stepping launch
+  int run_bs = 0, run_RB = 0;
   std::vector<int32_t> slot_R;             // run slot -> R of its group (Heun path)
   hipGraphExec_t graph_exec = nullptr;
   std::vector<int32_t> inst_order;         // run slot -> instance id
@@ -177,6 +181,7 @@ static int upload_geom(bpm_ctx* c, const MeshGroup& g, DevGeom<real>& d, Arena& 
   std::vector<real> V(g.V.begin(), g.V.end()), aif(g.aif.begin(), g.aif.end());
   HIPCHK(c, A.alloc(&d.rowptr, g.n + 1));
   HIPCHK(c, A.alloc(&d.col, g.nnz));
+  HIPCHK(c, A.alloc(&d.colx, g.nnz));
   HIPCHK(c, A.alloc(&d.layer, g.n));
   HIPCHK(c, A.alloc(&d.partner, g.n));
   HIPCHK(c, A.alloc(&d.K, g.nnz));
@@ -189,6 +194,11 @@ static int upload_geom(bpm_ctx* c, const MeshGroup& g, DevGeom<real>& d, Arena& 
   HIPCHK(c, A.alloc(&d.z, g.n));
   HIPCHK(c, hipMemcpy(d.rowptr, g.rowptr.data(), sizeof(int32_t) * (g.n + 1), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(d.col, g.col.data(), sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice));
+  {
+    std::vector<int32_t> colx(g.nnz);
+    for (int q = 0; q < g.nnz; ++q) colx[q] = g.col[q] | (g.layer[g.col[q]] << 16);
+    HIPCHK(c, hipMemcpy(d.colx, colx.data(), sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice));
+  }
   HIPCHK(c, hipMemcpy(d.layer, g.layer.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(d.partner, g.partner.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(d.K, K.data(), sizeof(real) * g.nnz, hipMemcpyHostToDevice));
@@ -466,16 +476,18 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     auto it = c->tune.find(tune_key(nmax, ninst, (int)sizeof(real) * 8));
     if (it != c->tune.end()) tuned_wg = it->second;
   }
-  const int bs = ((o->flags & BPM_FLAG_WG1024) || tuned_wg < 0) ? 1024 : 256;
+  const int bs = ((o->flags & BPM_FLAG_WG512) || tuned_wg < 0) ? 512 : 256;
   const size_t lds_budget = sym ? 48 * 1024 : 96 * 1024;
   int RB = (int)std::max<size_t>(1, std::min<size_t>(16, lds_budget / (sizeof(real) * (size_t)ldS_max)));
   RB = std::min(RB, Rmax);
   if ((size_t)RB * ldS_max * sizeof(real) > 120 * 1024)
     return fail(c, BPM_EINVAL, "bpm_run: island too large for the LDS staging of the demag product");
+  LdsPlan L{Rmax, (sym ? 2 : 1) * RB * ldS_max, 0, 0, 0, ldS_max};
   int per_cu = 0, cus = 0;
   {
-    hipError_t e = max_coresident<real>(sym ? 2 * RB : RB, ldS_max, fixed, bs, 0, &per_cu, &cus);
+    hipError_t e = max_coresident<real>(L, fixed, bs, &per_cu, &cus);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+    if (per_cu <= 0) return fail(c, BPM_EINVAL, "bpm_run: the stepping kernel does not fit a compute unit with this island size");
   }
   const int cap = std::max(1, per_cu * cus);
   std::vector<int> G(ng, 1);
@@ -503,26 +515,41 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     if (G[gi] > 1) coop = true;
   }
   if (coop && grid > cap) return fail(c, BPM_EINVAL, "bpm_run: workgroups per group exceed the resident capacity");
-  // stage the owned CSR rows in LDS for cooperative runs when the extra LDS keeps every
-  // workgroup resident
-  int csr_cap = 0;
+  // Cooperative runs keep the CSR rows and node data of the owned nodes in LDS and, when they fit
+  // with every workgroup still resident, the owned rows of S (with the largest RB that fits).
   if (coop) {
-    int own_max = 0;
+    int own_max = 0, nnz_max = 0;
     for (int gi = 0; gi < ng; ++gi) {
       const MeshGroup& g = *c->meshes[group_ids[gi]];
       for (int w = 0; w < G[gi]; ++w) {
         const int a = (int)((long long)g.n * w / G[gi]), b = (int)((long long)g.n * (w + 1) / G[gi]);
-        own_max = std::max(own_max, g.rowptr[b] - g.rowptr[a]);
+        own_max = std::max(own_max, b - a);
+        nnz_max = std::max(nnz_max, g.rowptr[b] - g.rowptr[a]);
       }
     }
-    const int want = own_max + 64;
-    if ((size_t)want * (7 * sizeof(real) + 8) <= 40 * 1024) {
-      int pc2 = 0, cu2 = 0;
-      if (max_coresident<real>(sym ? 2 * RB : RB, ldS_max, fixed, bs, want, &pc2, &cu2) == hipSuccess &&
-          pc2 * cu2 >= grid)
-        csr_cap = want;
+    auto fits = [&](const LdsPlan& T) {
+      if (dp5_lds_bytes<real>(T) > 160 * 1024) return false;
+      int pc = 0, cu = 0;
+      return max_coresident<real>(T, fixed, bs, &pc, &cu) == hipSuccess && pc * cu >= grid;
+    };
+    bool found = false;
+    if (!(o->flags & BPM_FLAG_STREAM_S) && !sym) {
+      for (int rb = std::min(Rmax, 16); rb >= 1 && !found; --rb) {
+        LdsPlan T{Rmax, rb * ldS_max, nnz_max + 64, own_max, own_max, ldS_max};
+        if (fits(T)) { L = T; RB = rb; found = true; }
+      }
+    }
+    if (!found) {
+      LdsPlan T = L;
+      T.csr_cap = nnz_max + 64;
+      T.own_cap = own_max;
+      if (fits(T)) L = T;
     }
   }
+  const int csr_cap = L.csr_cap;
+  c->run_plan = L;
+  c->run_bs = bs;
+  c->run_RB = RB;
   c->run_csr_cap = csr_cap;
   c->run_grid = grid;
   c->run_G = *std::max_element(G.begin(), G.end());
@@ -567,7 +594,7 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     v.ldS = (g.n + 15) / 16 * 16;
     v.wg0 = wg; v.G = G[gi];
     v.inst0 = c->group_inst0[mi]; v.sys0 = group_sys0[gi];
-    v.rowptr = d.rowptr; v.col = d.col; v.K = d.K; v.D = d.D; v.DT = d.DT;
+    v.rowptr = d.rowptr; v.col = d.col; v.colx = d.colx; v.K = d.K; v.D = d.D; v.DT = d.DT;
     v.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
     if (!v.S) return fail(c, BPM_EINVAL, "bpm_run: a mesh group does not keep S in the run precision");
     v.V = d.V; v.layer = d.layer; v.partner = d.partner; v.aif = d.aif;
@@ -579,9 +606,11 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     HIPCHK(c, A.alloc(&v.ys, 2 * R * st3));
     HIPCHK(c, A.alloc(&v.k, 7 * R * st3));
     HIPCHK(c, A.alloc(&v.yex, R * st3));
-    HIPCHK(c, A.alloc(&v.b, (size_t)R * g.n));
-    HIPCHK(c, A.alloc(&v.u, (size_t)R * g.n));
+    HIPCHK(c, A.alloc(&v.b, (size_t)R * v.ldS));
+    HIPCHK(c, A.alloc(&v.u, (size_t)R * v.ldS));
     HIPCHK(c, hipMemsetAsync(v.k, 0, sizeof(real) * 7 * R * st3, stream));
+    HIPCHK(c, hipMemsetAsync(v.b, 0, sizeof(real) * R * v.ldS, stream));   // padding stays zero
+    HIPCHK(c, hipMemsetAsync(v.u, 0, sizeof(real) * R * v.ldS, stream));
     v.bar = d_bar + gi;
     c->group_m[mi] = v.m;
     std::vector<real> m0(R * st3);
@@ -617,12 +646,12 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
 
   HIPCHK(c, hipEventRecord(c->ev0, stream));
   {
-    hipError_t e = launch_dp5<real>(d_groups, P, grid, RB, ldS_max, fixed, coop, stream, sym, bs, csr_cap);
+    hipError_t e = launch_dp5<real>(d_groups, P, grid, RB, L, fixed, coop, stream, bs);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("stepping kernel launch: ") + hipGetErrorString(e));
   }
   HIPCHK(c, hipEventRecord(c->ev1, stream));
   {
-    hipError_t e = launch_energy<real>(d_groups, d_imap, ninst, P, c->d_energy, ldS_max, nmax, stream);
+    hipError_t e = launch_energy<real>(d_groups, d_imap, ninst, P, c->d_energy, nmax, stream);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("energy kernel launch: ") + hipGetErrorString(e));
   }
   c->run_ninst = ninst;
@@ -827,7 +856,7 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
   for (int q = 0; q < n_cand; ++q) {
     bpm_run_opts p = *o;
     p.wg_per_group = cand[q] > 0 ? cand[q] : -cand[q];
-    p.flags = cand[q] > 0 ? (o->flags & ~BPM_FLAG_WG1024) : (o->flags | BPM_FLAG_WG1024);
+    p.flags = cand[q] > 0 ? (o->flags & ~BPM_FLAG_WG512) : (o->flags | BPM_FLAG_WG512);
     p.max_steps = probe_attempts;
     p.traj_cap = 0;
     int rc = bpm_run(c, &p, nullptr);
@@ -992,6 +1021,18 @@ int bpm_last_run_info(bpm_ctx* c, double* kernel_ms, int32_t* grid, int32_t* wg_
   if (kernel_ms) *kernel_ms = c->kernel_ms;
   if (grid) *grid = c->run_grid;
   if (wg_per_group) *wg_per_group = c->run_G;
+  return BPM_OK;
+}
+
+int bpm_last_run_layout(bpm_ctx* c, int32_t* threads_per_wg, int32_t* s_rows_lds, int32_t* csr_cap_lds,
+                        int32_t* rhs_block, int64_t* lds_bytes) {
+  if (!c) return BPM_EINVAL;
+  if (threads_per_wg) *threads_per_wg = c->run_bs;
+  if (s_rows_lds) *s_rows_lds = c->run_plan.s_rows;
+  if (csr_cap_lds) *csr_cap_lds = c->run_plan.csr_cap;
+  if (rhs_block) *rhs_block = c->run_RB;
+  if (lds_bytes) *lds_bytes = c->run_precision == 64 ? (int64_t)dp5_lds_bytes<double>(c->run_plan)
+                                                     : (int64_t)dp5_lds_bytes<float>(c->run_plan);
   return BPM_OK;
 }
 

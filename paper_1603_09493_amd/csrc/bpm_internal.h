@@ -95,6 +95,7 @@ struct GroupView {
   int inst0, sys0;            // first instance / system (contiguous)
   const int32_t* rowptr;
   const int32_t* col;
+  const int32_t* colx;        // col | layer(col) << 16 (n <= 65535)
   const real* K;
   const real* D;              // [nnz][3]
   const real* DT;             // [nnz][3]
@@ -113,8 +114,8 @@ struct GroupView {
   real* ys;                   // [R][3][n] stage input
   real* k;                    // [R][7][3][n]
   real* yex;                  // [R][3][n]
-  real* b;                    // [R][n]
-  real* u;                    // [R][n]
+  real* b;                    // [R][ldS], zero beyond n
+  real* u;                    // [R][ldS]
   unsigned long long* bar;    // group barrier counter
 };
 
@@ -137,6 +138,18 @@ struct RunParams {
   double* obs_acc;            // [ninst][2][6]: sum V mz soft, sum V mz hard, sum w m (3), max dev
   double* mom_acc;            // [ninst][2][3]
   const int2* wg_map;         // blockIdx -> (group, local wg)
+};
+
+// Dynamic LDS of one launch of the stepping kernel, in this order: instance constants
+// [ic_slots], demag right-hand sides [bl_elems], CSR rows of the owned nodes (csr_cap entries,
+// 0 = read from global memory), and the owned rows of S [s_rows][ldS] (0 = streamed).
+struct LdsPlan {
+  int32_t ic_slots;   // instance constants (the largest instance count of a group)
+  int32_t bl_elems;   // reals of the staged right-hand sides (RB [x2 for the symmetric product] x ldS)
+  int32_t csr_cap;    // CSR entries of the owned rows (0: CSR and node data read from global memory)
+  int32_t own_cap;    // owned nodes (node data staged beside the CSR rows)
+  int32_t s_rows;     // rows of S kept in LDS (0: S streamed from global memory)
+  int32_t ldS;        // largest row stride of S in the launch
 };
 
 std::string hip_err_string(hipError_t e);

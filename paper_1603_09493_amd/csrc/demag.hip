@@ -114,11 +114,11 @@ int demag_assemble_device(MeshGroup& g, double beta, hipStream_t stream, std::st
     CHK(hipGetLastError());
   }
   CHK(hipStreamSynchronize(stream));
-  hipFree(dtc); hipFree(dptr); hipFree(dn2t); hipFree(dwt); hipFree(dGT);
+  (void)hipFree(dtc); (void)hipFree(dptr); (void)hipFree(dn2t); (void)hipFree(dwt); (void)hipFree(dGT);
   return BPM_OK;
 fail:
   err = std::string("demag assembly: ") + hipGetErrorString(e);
-  hipFree(dtc); hipFree(dptr); hipFree(dn2t); hipFree(dwt); hipFree(dGT);
+  (void)hipFree(dtc); (void)hipFree(dptr); (void)hipFree(dn2t); (void)hipFree(dwt); (void)hipFree(dGT);
   return BPM_EHIP;
 #undef CHK
 }

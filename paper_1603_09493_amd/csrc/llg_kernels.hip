@@ -14,6 +14,13 @@
 //      LLG right-hand side, the next stage input, and the reductions of the step control
 // The step decision (per system: one instance, or several dipole-coupled instances) is taken
 // redundantly by every workgroup of the group from the same reduced values.
+//
+// Memory-level parallelism is the design constraint at these sizes: a field evaluation of a
+// 2k-node island is a few MB of traffic spread over up to 256 workgroups, so every phase issues
+// its independent loads together (staged right-hand sides in wide vectors, CSR gathers in
+// batches, stage combinations with a compile-time stage count) instead of one latency per
+// element.  Instance constants, the CSR rows and node data of the owned nodes, and - when they
+// fit - the owned rows of S stay in LDS for the whole launch.
 #include <cmath>
 #include <type_traits>
 
@@ -34,6 +41,8 @@ __constant__ double kC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0}
 // error weights: 5th-order minus embedded 4th-order weights
 __constant__ double kE[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200,
                              22.0 / 525, -1.0 / 40};
+
+constexpr int kGather = 8;   // CSR entries whose gathers are issued together
 
 // ---------------------------------------------------------------------------------------------
 // small device helpers
@@ -69,7 +78,6 @@ __device__ __forceinline__ double vcomp(const double2& v, int q) { return q == 0
 
 // instances handled at once in the demag product, and vector loads per lane in flight
 template <int BS> struct PhaseBShape { static constexpr int RMAX = 16, U = 8; };
-template <> struct PhaseBShape<1024> { static constexpr int RMAX = 8, U = 2; };
 
 struct GroupSync {
   unsigned long long* ctr;
@@ -134,6 +142,7 @@ struct Ctl {
   int crossed[kMaxInstPerGroup];
   long long ntraj[kMaxInstPerGroup];
   double Bdip[kMaxInstPerGroup][3];
+  double mom[kMaxInstPerGroup][3];
   double red[16];
   // per-instance / per-system partial sums of one workgroup (LDS atomics), pushed to global once
   double accL[kMaxInstPerGroup][6];
@@ -141,8 +150,10 @@ struct Ctl {
   int any_active, any_coupled;
 };
 
-// CSR rows of the owned nodes [i0, i1): rp[k] .. rp[k+1] index col/K/D/DT for node i0 + k, either
-// in global memory (rp = rowptr + i0) or staged once into LDS (rebased to zero).
+// CSR rows and node data of the owned nodes [i0, i1), indexed by k = i - i0 (rp, pt, lay, V,
+// aif, x, y) or by the CSR position (col, K, D, DT): either global memory (rp = rowptr + i0,
+// node arrays offset by i0) or staged once into LDS (rp rebased to zero).  col holds the node
+// index in its low 16 bits and that node's layer above.
 template <typename real>
 struct Csr {
   const int32_t* rp;
@@ -150,55 +161,100 @@ struct Csr {
   const real* K;
   const real* D;
   const real* DT;
+  const int32_t* pt;
+  const int32_t* lay;
+  const real* V;
+  const real* aif;
+  const double* x;
+  const double* y;
 };
 
+// LDS bytes of the staged CSR rows (cap entries) and node data (ocap nodes), 16-byte multiple
 template <typename real>
-struct Ptrs {
-  real* m;
-  real* ys;     // two buffers: [2][R][3][n]
-  real* k;      // [R][7][3][n]
-  real* yex;
-  real* b;
-  real* u;
-};
+__host__ __device__ inline size_t csr_stage_bytes(int cap, int ocap) {
+  if (cap <= 0) return 0;
+  const size_t b = (size_t)ocap * 2 * sizeof(double) + (size_t)cap * 7 * sizeof(real) + (size_t)ocap * 2 * sizeof(real) +
+                   (size_t)cap * sizeof(int32_t) + (size_t)(ocap + 1) * sizeof(int32_t) + (size_t)ocap * 2 * sizeof(int32_t);
+  return (b + 15) / 16 * 16;
+}
+
+static_assert(sizeof(InstConst) % 16 == 0, "instance constants are copied to LDS in 16-byte words");
+__host__ __device__ inline size_t ic_stage_bytes(int slots) { return (size_t)slots * sizeof(InstConst); }
+
+template <typename real>
+__host__ __device__ inline size_t lds_plan_bytes(const LdsPlan& L) {
+  return ic_stage_bytes(L.ic_slots) + ((size_t)L.bl_elems * sizeof(real) + 15) / 16 * 16 +
+         csr_stage_bytes<real>(L.csr_cap, L.own_cap) + (size_t)L.s_rows * L.ldS * sizeof(real);
+}
+
+// copy `cnt` 16-byte words, all loads of a thread in flight before its stores
+template <int BS>
+__device__ __forceinline__ void copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int cnt) {
+  constexpr int UN = 8;
+  for (int base = threadIdx.x; base < cnt; base += BS * UN) {
+    uint4 v[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int q = base + u * BS;
+      v[u] = src[q < cnt ? q : cnt - 1];   // in bounds on every lane; stored only where q < cnt
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int q = base + u * BS;
+      if (q < cnt) dst[q] = v[u];
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------------------------
 // phase A: yex = K y, b = D (Ms y), dipole moments
 // ---------------------------------------------------------------------------------------------
 template <typename real, int BS>
-__device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParams& P, Ctl& c, int i0, int i1,
-                        const real* __restrict__ ysrc, int ev, const Csr<real>& cs) {
-  const int n = g.n, nown = i1 - i0;
+__device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
+                                        int i0, int i1, const real* __restrict__ ysrc, int ev, const Csr<real>& cs) {
+  const int n = g.n, nown = i1 - i0, ldS = g.ldS;
   if (c.any_coupled) {
     for (int q = threadIdx.x; q < g.R * 3; q += BS) c.accL[q / 3][q % 3] = 0.0;
     __syncthreads();
   }
   // every (instance, owned node) pair in one pass
   for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
-    const int r = it2 / nown, i = i0 + (it2 - r * nown);
+    const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
     if (!c.active[c.isys[r]]) continue;
-    const InstConst& ic = P.inst[g.inst0 + r];
-    const real Ms0 = (real)ic.Ms[0], Ms1 = (real)ic.Ms[1];
+    const real Ms0 = (real)icL[r].Ms[0], Ms1 = (real)icL[r].Ms[1];
     const real* y = ysrc + (size_t)r * 3 * n;
     real ex0 = 0, ex1 = 0, ex2 = 0, bb = 0;
-    const int q1 = cs.rp[i - i0 + 1];
-    for (int q = cs.rp[i - i0]; q < q1; ++q) {
-      const int j = cs.col[q];
-      const real kq = cs.K[q];
-      const real yx = y[j], yy = y[n + j], yz = y[2 * n + j];
-      ex0 += kq * yx;
-      ex1 += kq * yy;
-      ex2 += kq * yz;
-      const real Msj = g.layer[j] ? Ms1 : Ms0;
-      bb += Msj * (cs.D[3 * q] * yx + cs.D[3 * q + 1] * yy + cs.D[3 * q + 2] * yz);
+    const int qa = cs.rp[k], qb = cs.rp[k + 1];
+    for (int q0 = qa; q0 < qb; q0 += kGather) {
+      int cj[kGather];
+      real yx[kGather], yy[kGather], yz[kGather];
+#pragma unroll
+      for (int u = 0; u < kGather; ++u) cj[u] = q0 + u < qb ? cs.col[q0 + u] : i;
+#pragma unroll
+      for (int u = 0; u < kGather; ++u) {
+        const int j = cj[u] & 0xFFFF;
+        yx[u] = y[j]; yy[u] = y[n + j]; yz[u] = y[2 * n + j];
+      }
+#pragma unroll
+      for (int u = 0; u < kGather; ++u) {
+        const int q = q0 + u;
+        if (q < qb) {
+          const real kq = cs.K[q];
+          ex0 += kq * yx[u];
+          ex1 += kq * yy[u];
+          ex2 += kq * yz[u];
+          const real Msj = (cj[u] >> 16) ? Ms1 : Ms0;
+          bb += Msj * (cs.D[3 * q] * yx[u] + cs.D[3 * q + 1] * yy[u] + cs.D[3 * q + 2] * yz[u]);
+        }
+      }
     }
     real* yex = g.yex + (size_t)r * 3 * n;
     yex[i] = ex0;
     yex[n + i] = ex1;
     yex[2 * n + i] = ex2;
-    g.b[(size_t)r * n + i] = bb;
+    g.b[(size_t)r * ldS + i] = bb;
     if (c.coupled[r]) {
-      const double w = (double)(g.layer[i] ? Ms1 : Ms0) * (double)g.V[i];
+      const double w = (double)(cs.lay[k] ? Ms1 : Ms0) * (double)cs.V[k];
       atomicAdd(&c.accL[r][0], w * (double)y[i]);
       atomicAdd(&c.accL[r][1], w * (double)y[n + i]);
       atomicAdd(&c.accL[r][2], w * (double)y[2 * n + i]);
@@ -215,12 +271,15 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
 }
 
 // ---------------------------------------------------------------------------------------------
-// phase B: u = S b for the owned rows; b of up to RB instances staged in LDS
+// phase B: u = S b for the owned rows; b of up to RB instances staged in LDS.  kSL: the owned
+// rows of S are resident in LDS (SL, row k = node i0 + k), else they stream from global memory.
 // ---------------------------------------------------------------------------------------------
-template <typename real, int BS>
-__device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* bL, int RB) {
-  const int n = g.n, ldS = g.ldS;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = BS / 64;
+template <typename real, int BS, bool kSL>
+__device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* bL,
+                                        const real* SL, int RB) {
+  const int ldS = g.ldS;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int nw = BS / 64;
   constexpr int VEC = 16 / sizeof(real);
   constexpr int U = PhaseBShape<BS>::U;           // vector loads per lane in flight per row chunk
   constexpr int RMAX = PhaseBShape<BS>::RMAX;
@@ -233,13 +292,12 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
     for (int r = rb; r < rb + rn; ++r) any = any || c.active[c.isys[r]];
     if (!any) continue;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) {
-      const int r = idx / ldS, l = idx - r * ldS;
-      bL[idx] = l < n ? g.b[(size_t)(rb + r) * n + l] : (real)0;
-    }
+    // b rows are ldS long (zero padded), so the staging is one contiguous 16-byte copy
+    copy16<BS>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const uint4*>(g.b + (size_t)rb * ldS),
+               rn * ldS / VEC);
     __syncthreads();
     for (int row = i0 + wid; row < i1; row += nw) {
-      const real* Srow = g.S + (size_t)row * ldS;
+      const real* Srow = kSL ? SL + (size_t)(row - i0) * ldS : g.S + (size_t)row * ldS;
       real acc[RMAX];
 #pragma unroll
       for (int r = 0; r < RMAX; ++r) acc[r] = 0;
@@ -269,7 +327,7 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
       for (int r = 0; r < RMAX; ++r) {
         if (r < rn) {
           const real v = wave_sum(acc[r]);
-          if (lane == 0) g.u[(size_t)(rb + r) * n + row] = v;
+          if (lane == 0) g.u[(size_t)(rb + r) * ldS + row] = v;
         }
       }
     }
@@ -283,7 +341,8 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
 template <typename real, int BS>
 __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, real* bL, int RB) {
   const int n = g.n, ldS = g.ldS;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = BS / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int nw = BS / 64;
   constexpr int VEC = 16 / sizeof(real);
   constexpr int U = 4;
   constexpr int RMAX = PhaseBShape<BS>::RMAX;
@@ -297,11 +356,9 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
     for (int r = rb; r < rb + rn; ++r) any = any || c.active[c.isys[r]];
     if (!any) continue;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) {
-      const int r = idx / ldS, l = idx - r * ldS;
-      bL[idx] = l < n ? g.b[(size_t)(rb + r) * n + l] : (real)0;
-      uL[idx] = (real)0;
-    }
+    copy16<BS>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const uint4*>(g.b + (size_t)rb * ldS),
+               rn * ldS / VEC);
+    for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) uL[idx] = (real)0;
     __syncthreads();
     for (int k = wid; k < n; k += nw) {
       const real* Srow = g.S + (size_t)k * ldS;
@@ -350,39 +407,68 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
     __syncthreads();
     for (int idx = threadIdx.x; idx < rn * n; idx += BS) {
       const int r = idx / n, l = idx - r * n;
-      g.u[(size_t)(rb + r) * n + l] = uL[r * ldS + l];
+      g.u[(size_t)(rb + r) * ldS + l] = uL[r * ldS + l];
     }
   }
+}
+
+// next stage input of stage S+1: m + sum_{l<S} (h a_{S+1,l}) k_l + (h a_{S+1,S}) k_S, with all
+// loads of the previous stages issued together
+template <typename real, int S>
+__device__ __forceinline__ void stage_input(const real* __restrict__ kr, const real* __restrict__ m, size_t st3,
+                                            int n, int i, double h, real kx, real ky, real kz, real* v) {
+  real kl[S > 0 ? S : 1][3];
+  real mm[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) mm[d] = m[d * n + i];
+#pragma unroll
+  for (int l = 0; l < S; ++l)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) kl[l][d] = kr[(size_t)l * st3 + d * n + i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    real acc = 0;
+#pragma unroll
+    for (int l = 0; l < S; ++l) acc += (real)(h * kA[S + 1][l]) * kl[l][d];
+    v[d] = mm[d] + acc;
+  }
+  const real ha = (real)(h * kA[S + 1][S]);
+  v[0] += ha * kx; v[1] += ha * ky; v[2] += ha * kz;
 }
 
 // ---------------------------------------------------------------------------------------------
 // phase C: effective field, LLG right-hand side, next stage input, reductions
 // ---------------------------------------------------------------------------------------------
 template <typename real, bool kFixed, int BS>
-__device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParams& P, Ctl& c, int i0, int i1,
-                        int s, const real* __restrict__ ysrc, real* __restrict__ ydst, int it, int ev,
-                        const Csr<real>& cs) {
-  const int n = g.n, nown = i1 - i0;
+__device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
+                                        int i0, int i1, int s, const real* __restrict__ ysrc,
+                                        real* __restrict__ ydst, int it, int ev, const Csr<real>& cs) {
+  const int n = g.n, nown = i1 - i0, ldS = g.ldS;
   const size_t st3 = (size_t)3 * n;
   // dipole fields of coupled instances from the moments of this stage
   if (c.any_coupled) {
+    for (int q = threadIdx.x; q < g.R * 3; q += BS)
+      c.mom[q / 3][q % 3] = P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + ev % 3) * 3 + q % 3];
+    __syncthreads();
     for (int J = threadIdx.x; J < g.R; J += BS) {
-      c.Bdip[J][0] = c.Bdip[J][1] = c.Bdip[J][2] = 0.0;
-      if (!c.coupled[J]) continue;
-      const InstConst& cj = P.inst[g.inst0 + J];
-      for (int I = 0; I < g.R; ++I) {
-        if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
-        const InstConst& ci = P.inst[g.inst0 + I];
-        const double* mu = &P.mom_acc[((size_t)(g.inst0 + I) * 3 + ev % 3) * 3];
-        const double d0 = cj.off[0] - ci.off[0], d1 = cj.off[1] - ci.off[1], d2 = cj.off[2] - ci.off[2];
-        const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double e0 = d0 / rr, e1 = d1 / rr, e2 = d2 / rr;
-        const double mr = mu[0] * e0 + mu[1] * e1 + mu[2] * e2;
-        const double f = kMu0 / (4.0 * kPi * rr * rr * rr);
-        c.Bdip[J][0] += f * (3.0 * mr * e0 - mu[0]);
-        c.Bdip[J][1] += f * (3.0 * mr * e1 - mu[1]);
-        c.Bdip[J][2] += f * (3.0 * mr * e2 - mu[2]);
+      double B0 = 0.0, B1 = 0.0, B2 = 0.0;
+      if (c.coupled[J]) {
+        const InstConst& cj = icL[J];
+        for (int I = 0; I < g.R; ++I) {
+          if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
+          const InstConst& ci = icL[I];
+          const double* mu = c.mom[I];
+          const double d0 = cj.off[0] - ci.off[0], d1 = cj.off[1] - ci.off[1], d2 = cj.off[2] - ci.off[2];
+          const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          const double e0 = d0 / rr, e1 = d1 / rr, e2 = d2 / rr;
+          const double mr = mu[0] * e0 + mu[1] * e1 + mu[2] * e2;
+          const double f = kMu0 / (4.0 * kPi * rr * rr * rr);
+          B0 += f * (3.0 * mr * e0 - mu[0]);
+          B1 += f * (3.0 * mr * e1 - mu[1]);
+          B2 += f * (3.0 * mr * e2 - mu[2]);
+        }
       }
+      c.Bdip[J][0] = B0; c.Bdip[J][1] = B1; c.Bdip[J][2] = B2;
     }
   }
   if (s >= 5) {
@@ -392,49 +478,60 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
   __syncthreads();
   const real rtol = (real)P.rtol, atol = (real)P.atol;
   for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
-    const int r = it2 / nown, i = i0 + (it2 - r * nown);
+    const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
     const int sl = c.isys[r];
     if (!c.active[sl]) continue;
-    const InstConst& ic = P.inst[g.inst0 + r];
+    const InstConst& ic = icL[r];
     const double h = c.h[sl];
     const double ts = c.t[sl] + kC[s] * h;
     const real* y = ysrc + (size_t)r * st3;
     const real* yex = g.yex + (size_t)r * st3;
-    const real* u = g.u + (size_t)r * n;
+    const real* u = g.u + (size_t)r * ldS;
     real* kr = g.k + (size_t)r * 7 * st3;
     const real* m = g.m + (size_t)r * st3;
     real* yn = ydst + (size_t)r * st3;
     const real gp = (real)ic.gp, al = (real)ic.alpha;
-    const int L = g.layer[i];
-    const real Vi = g.V[i];
+    const int L = cs.lay[k];
+    const real Vi = cs.V[k];
+    const int p = cs.pt[k];
     const real mx = y[i], my = y[n + i], mz = y[2 * n + i];
+    const real ex0 = yex[i], ex1 = yex[n + i], ex2 = yex[2 * n + i];
+    const int pp = p >= 0 ? p : i;
+    const real px = y[pp], py = y[n + pp], pz = y[2 * n + pp];
+    // demag: -mu0 / V_i (D^T u)_i, gathers of u issued in batches
+    real dx = 0, dy = 0, dz = 0;
+    const int qa = cs.rp[k], qb = cs.rp[k + 1];
+    for (int q0 = qa; q0 < qb; q0 += kGather) {
+      real uq[kGather];
+#pragma unroll
+      for (int w = 0; w < kGather; ++w) uq[w] = u[q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i];
+#pragma unroll
+      for (int w = 0; w < kGather; ++w) {
+        const int q = q0 + w;
+        if (q < qb) {
+          dx += cs.DT[3 * q] * uq[w];
+          dy += cs.DT[3 * q + 1] * uq[w];
+          dz += cs.DT[3 * q + 2] * uq[w];
+        }
+      }
+    }
     // exchange
     const real cex = -(real)ic.cex[L] / Vi;
-    real Bx = cex * yex[i], By = cex * yex[n + i], Bz = cex * yex[2 * n + i];
+    real Bx = cex * ex0, By = cex * ex1, Bz = cex * ex2;
     // anisotropy
     const real ux = (real)ic.axis[L][0], uy = (real)ic.axis[L][1], uz = (real)ic.axis[L][2];
     const real mu = (real)ic.can[L] * (mx * ux + my * uy + mz * uz);
     Bx += mu * ux; By += mu * uy; Bz += mu * uz;
     // interlayer
-    const int p = g.partner[i];
     if (p >= 0) {
-      const real ci = (real)ic.cint[L] * g.aif[i] / Vi;
-      Bx += ci * y[p]; By += ci * y[n + p]; Bz += ci * y[2 * n + p];
-    }
-    // demag: -mu0 / V_i (D^T u)_i
-    real dx = 0, dy = 0, dz = 0;
-    const int q1 = cs.rp[i - i0 + 1];
-    for (int q = cs.rp[i - i0]; q < q1; ++q) {
-      const real uq = u[cs.col[q]];
-      dx += cs.DT[3 * q] * uq;
-      dy += cs.DT[3 * q + 1] * uq;
-      dz += cs.DT[3 * q + 2] * uq;
+      const real ci = (real)ic.cint[L] * cs.aif[k] / Vi;
+      Bx += ci * px; By += ci * py; Bz += ci * pz;
     }
     const real cd = -(real)kMu0 / Vi;
     Bx += cd * dx; By += cd * dy; Bz += cd * dz;
     // Zeeman (+ dipoles)
     double zx, zy, zz;
-    applied_B(ic, ts, g.x[i] + ic.off[0], g.y[i] + ic.off[1], zx, zy, zz);
+    applied_B(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
     if (c.coupled[r]) { zx += c.Bdip[r][0]; zy += c.Bdip[r][1]; zz += c.Bdip[r][2]; }
     Bx += (real)zx; By += (real)zy; Bz += (real)zz;
     // LLG: dm/dt = -gp [ m x B + alpha m x (m x B) ]
@@ -446,14 +543,14 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
     if (s < 6) {
       // next stage input m + h sum_l a_{s+1,l} k_l (stage 7 input = 5th-order solution)
       real v[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        real acc = 0;
-        for (int l = 0; l < s; ++l) acc += (real)(h * kA[s + 1][l]) * kr[(size_t)l * st3 + d * n + i];
-        v[d] = m[d * n + i] + acc;
+      switch (s) {
+        case 0: stage_input<real, 0>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
+        case 1: stage_input<real, 1>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
+        case 2: stage_input<real, 2>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
+        case 3: stage_input<real, 3>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
+        case 4: stage_input<real, 4>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
+        default: stage_input<real, 5>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
       }
-      const real ha = (real)(h * kA[s + 1][s]);
-      v[0] += ha * kx; v[1] += ha * ky; v[2] += ha * kz;
       yn[i] = v[0]; yn[n + i] = v[1]; yn[2 * n + i] = v[2];
       if (s == 5) {
         // observables of the normalised candidate
@@ -469,15 +566,21 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
       }
     } else {
       // error estimate h sum_l e_l k_l, scaled per component
+      real kl[6][3];
+#pragma unroll
+      for (int l = 0; l < 6; ++l)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) kl[l][d] = kr[(size_t)l * st3 + d * n + i];
+      const real y0[3] = {m[i], m[n + i], m[2 * n + i]};
       real e[3] = {0, 0, 0};
+#pragma unroll
       for (int l = 0; l < 6; ++l) {
         const real he = (real)(h * kE[l]);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) e[d] += he * kr[(size_t)l * st3 + d * n + i];
+        for (int d = 0; d < 3; ++d) e[d] += he * kl[l][d];
       }
       const real he6 = (real)(h * kE[6]);
       e[0] += he6 * kx; e[1] += he6 * ky; e[2] += he6 * kz;
-      const real y0[3] = {m[i], m[n + i], m[2 * n + i]};
       const real y1[3] = {mx, my, mz};
       double es = 0.0;
 #pragma unroll
@@ -508,25 +611,26 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
 }
 
 template <typename real, bool kFixed, int BS>
-__device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunParams& P, Ctl& c, GroupSync& gs,
-                           int i0, int i1, int s, const real* ysrc, real* ydst, int it, int ev,
-                           real* bL, int RB, const Csr<real>& cs) {
-  phase_A<real, BS>(g, P, c, i0, i1, ysrc, ev, cs);
+__device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
+                                           GroupSync& gs, int i0, int i1, int s, const real* ysrc, real* ydst,
+                                           int it, int ev, real* bL, const real* SL, int RB, const Csr<real>& cs) {
+  phase_A<real, BS>(g, P, c, icL, i0, i1, ysrc, ev, cs);
   group_sync(gs);
-  if (g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real, BS>(g, c, bL, RB);
-  else phase_B<real, BS>(g, c, i0, i1, bL, RB);
+  if (SL) phase_B<real, BS, true>(g, c, i0, i1, bL, SL, RB);
+  else if (g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real, BS>(g, c, bL, RB);
+  else phase_B<real, BS, false>(g, c, i0, i1, bL, nullptr, RB);
   group_sync(gs);
-  phase_C<real, kFixed, BS>(g, P, c, i0, i1, s, ysrc, ydst, it, ev, cs);
+  phase_C<real, kFixed, BS>(g, P, c, icL, i0, i1, s, ysrc, ydst, it, ev, cs);
   group_sync(gs);
 }
 
 // trajectory sample of instance r (called by one thread of the group's first workgroup)
 template <typename real, int BS>
-__device__ __forceinline__ void save_sample(const GroupView<real>& g, const RunParams& P, Ctl& c, int r, double t,
-                            double dt, double err, const double* ob) {
+__device__ __forceinline__ void save_sample(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
+                                            int r, double t, double dt, double err, const double* ob) {
   if (P.traj_cap <= 0 || c.ntraj[r] >= P.traj_cap) return;
   const int gi = g.inst0 + r;
-  const InstConst& ic = P.inst[gi];
+  const InstConst& ic = icL[r];
   double bx, by, bz;
   applied_B(ic, t, g.cen[0] + ic.off[0], g.cen[1] + ic.off[1], bx, by, bz);
   double* smp = P.traj + ((size_t)gi * P.traj_cap + c.ntraj[r]) * kTrajW;
@@ -543,11 +647,10 @@ __device__ __forceinline__ void save_sample(const GroupView<real>& g, const RunP
   c.ntraj[r]++;
 }
 
-// set the step size of the coming attempt and write the stage-2 input
-template <typename real, bool kFixed, int BS>
-__device__ __forceinline__ void begin_attempt(const GroupView<real>& g, const RunParams& P, Ctl& c, int i0, int i1,
-                              real* ydst, long long nfix) {
-  for (int sl = threadIdx.x; sl < g.nsys; sl += BS) {
+// step size of the coming attempt of every active system
+template <bool kFixed, int BS>
+__device__ __forceinline__ void plan_attempt(const RunParams& P, Ctl& c, int nsys, long long nfix) {
+  for (int sl = threadIdx.x; sl < nsys; sl += BS) {
     if (!c.active[sl]) continue;
     c.last[sl] = 0;
     if (kFixed) {
@@ -562,60 +665,74 @@ __device__ __forceinline__ void begin_attempt(const GroupView<real>& g, const Ru
       c.h[sl] = h;
     }
   }
-  __syncthreads();
-  const int n = g.n, nown = i1 - i0;
-  const size_t st3 = (size_t)3 * n;
-  for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
-    const int r = it2 / nown, i = i0 + (it2 - r * nown);
-    const int sl = c.isys[r];
-    if (!c.active[sl]) continue;
-    const real ha = (real)(c.h[sl] * kA[1][0]);
-    const real* m = g.m + (size_t)r * st3;
-    const real* k0 = g.k + (size_t)r * 7 * st3;
-    real* yn = ydst + (size_t)r * st3;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) yn[d * n + i] = m[d * n + i] + ha * k0[d * n + i];
-  }
 }
 
 template <typename real, bool kFixed, int BS>
 __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restrict__ groups,
-                                                     RunParams P, int RB, int bl_elems, int csr_cap) {
+                                                 RunParams P, int RB, LdsPlan LP) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  real* bL = reinterpret_cast<real*>(smem_raw);
   __shared__ Ctl c;
   const int2 gm = P.wg_map[blockIdx.x];
   const GroupView<real> g = groups[gm.x];
   const int w = gm.y;
-  const int n = g.n;
+  const int n = g.n, ldS = g.ldS;
   const int i0 = (int)((long long)n * w / g.G), i1 = (int)((long long)n * (w + 1) / g.G);
+  const int nown = i1 - i0;
   const size_t st3 = (size_t)3 * n;
   const size_t ybuf = (size_t)g.R * st3;
   GroupSync gs{g.bar, 0ull, g.G};
   const bool lead = (w == 0);
-  // CSR rows of the owned nodes: staged in LDS when they fit the budget of this launch
-  Csr<real> cs{g.rowptr + i0, g.col, g.K, g.D, g.DT};
+  // ---- dynamic LDS: instance constants, staged right-hand sides, CSR rows, S rows
+  unsigned char* lp = smem_raw;
+  InstConst* icL = reinterpret_cast<InstConst*>(lp);
+  lp += ic_stage_bytes(LP.ic_slots);
+  real* bL = reinterpret_cast<real*>(lp);
+  lp += ((size_t)LP.bl_elems * sizeof(real) + 15) / 16 * 16;
+  unsigned char* csr_lds = lp;
+  lp += csr_stage_bytes<real>(LP.csr_cap, LP.own_cap);
+  // S rows are resident only when this workgroup's rows fit the planned area
+  real* SL = (LP.s_rows > 0 && nown <= LP.s_rows) ? reinterpret_cast<real*>(lp) : nullptr;
+  copy16<BS>(reinterpret_cast<uint4*>(icL), reinterpret_cast<const uint4*>(P.inst + g.inst0),
+             (int)(g.R * sizeof(InstConst) / 16));
+  if (SL) {
+    // the owned rows of S, once for the whole launch
+    constexpr int VEC = 16 / sizeof(real);
+    copy16<BS>(reinterpret_cast<uint4*>(SL), reinterpret_cast<const uint4*>(g.S + (size_t)i0 * ldS), nown * ldS / VEC);
+  }
+  Csr<real> cs{g.rowptr + i0, g.colx, g.K, g.D, g.DT, g.partner + i0, g.layer + i0, g.V + i0, g.aif + i0, g.x + i0, g.y + i0};
   {
     const int q0 = g.rowptr[i0], nq = g.rowptr[i1] - q0;
-    if (csr_cap > 0 && nq <= csr_cap && (i1 - i0) < csr_cap) {
-      real* KL = bL + bl_elems;                  // [cap]
-      real* DL = KL + csr_cap;                   // [cap][3]
-      real* DTL = DL + 3 * csr_cap;              // [cap][3]
-      int32_t* colL = reinterpret_cast<int32_t*>(DTL + 3 * csr_cap);   // [cap]
-      int32_t* rpL = colL + csr_cap;             // [cap + 1]
+    if (LP.csr_cap > 0 && nq <= LP.csr_cap && nown <= LP.own_cap) {
+      const int cap = LP.csr_cap, ocap = LP.own_cap;
+      double* xL = reinterpret_cast<double*>(csr_lds);
+      double* yL = xL + ocap;
+      real* KL = reinterpret_cast<real*>(yL + ocap);
+      real* DL = KL + cap;
+      real* DTL = DL + 3 * cap;
+      real* VL = DTL + 3 * cap;
+      real* aL = VL + ocap;
+      int32_t* colL = reinterpret_cast<int32_t*>(aL + ocap);
+      int32_t* rpL = colL + cap;
+      int32_t* ptL = rpL + ocap + 1;
+      int32_t* layL = ptL + ocap;
       for (int q = threadIdx.x; q < nq; q += BS) {
-        colL[q] = g.col[q0 + q];
+        colL[q] = g.colx[q0 + q];
         KL[q] = g.K[q0 + q];
         for (int d = 0; d < 3; ++d) {
           DL[3 * q + d] = g.D[3 * (q0 + q) + d];
           DTL[3 * q + d] = g.DT[3 * (q0 + q) + d];
         }
       }
-      for (int k = threadIdx.x; k <= i1 - i0; k += BS) rpL[k] = g.rowptr[i0 + k] - q0;
-      cs = Csr<real>{rpL, colL, KL, DL, DTL};
-      __syncthreads();
+      for (int k = threadIdx.x; k <= nown; k += BS) rpL[k] = g.rowptr[i0 + k] - q0;
+      for (int k = threadIdx.x; k < nown; k += BS) {
+        ptL[k] = g.partner[i0 + k]; layL[k] = g.layer[i0 + k];
+        VL[k] = g.V[i0 + k]; aL[k] = g.aif[i0 + k];
+        xL[k] = g.x[i0 + k]; yL[k] = g.y[i0 + k];
+      }
+      cs = Csr<real>{rpL, colL, KL, DL, DTL, ptL, layL, VL, aL, xL, yL};
     }
   }
+  __syncthreads();
   const long long nfix = kFixed ? (long long)ceil(P.t_end / P.dt_fixed - 1e-9) : 0;
 
   // ---- init control state
@@ -629,7 +746,7 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
   if (threadIdx.x == 0) {
     c.any_coupled = 0;
     for (int r = 0; r < g.R; ++r) {
-      const int sl = P.inst[g.inst0 + r].sys - g.sys0;
+      const int sl = icL[r].sys - g.sys0;
       c.isys[r] = sl;
       c.ninst[sl] += 1;
       c.coupled[r] = P.sys[g.sys0 + sl].coupled;
@@ -644,11 +761,11 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
   real* ys1 = g.ys + ybuf;
   for (int q = threadIdx.x; q < g.R * 6; q += BS) c.accL[q / 6][q % 6] = 0.0;
   __syncthreads();
-  for (int it2 = threadIdx.x; it2 < g.R * (i1 - i0); it2 += BS) {
-    const int r = it2 / (i1 - i0), i = i0 + (it2 - r * (i1 - i0));
-    const InstConst& ic = P.inst[g.inst0 + r];
-    const int L = g.layer[i];
-    const double Vd = (double)g.V[i], Ms = ic.Ms[L];
+  for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
+    const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
+    const InstConst& ic = icL[r];
+    const int L = cs.lay[k];
+    const double Vd = (double)cs.V[k], Ms = ic.Ms[L];
     real v[3];
     for (int d = 0; d < 3; ++d) {
       v[d] = g.m[(size_t)r * st3 + d * n + i];
@@ -664,7 +781,7 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
     atomicAdd(&P.obs_acc[((size_t)(g.inst0 + q / 5) * 3 + 2) * 6 + q % 5], c.accL[q / 5][q % 5]);
   group_sync(gs);
   int ev = 0;
-  field_eval<real, kFixed, BS>(g, P, c, gs, i0, i1, 0, ys0, ys1, 2, ev++, bL, RB, cs);
+  field_eval<real, kFixed, BS>(g, P, c, icL, gs, i0, i1, 0, ys0, ys1, 2, ev++, bL, SL, RB, cs);
   // initial observables, crossing state, first trajectory sample
   for (int r = threadIdx.x; r < g.R; r += BS) {
     const double* ob = &P.obs_acc[((size_t)(g.inst0 + r) * 3 + 2) * 6];
@@ -672,10 +789,22 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
     c.prev_t[r] = 0.0; c.prev_v[r] = vh;
     c.mzs[r] = g.Vsoft > 0 ? ob[0] / g.Vsoft : 0.0; c.mzh[r] = vh;
     if (vh <= 0.0) { c.crossed[r] = 1; c.tsw[r] = 0.0; }
-    if (lead) save_sample<real, BS>(g, P, c, r, 0.0, 0.0, 0.0, ob);
+    if (lead) save_sample<real, BS>(g, P, c, icL, r, 0.0, 0.0, 0.0, ob);
   }
   __syncthreads();
-  begin_attempt<real, kFixed, BS>(g, P, c, i0, i1, ys1, nfix);
+  plan_attempt<kFixed, BS>(P, c, g.nsys, nfix);
+  __syncthreads();
+  for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
+    const int r = it2 / nown, i = i0 + (it2 - r * nown);
+    const int sl = c.isys[r];
+    if (!c.active[sl]) continue;
+    const real ha = (real)(c.h[sl] * kA[1][0]);
+    const real* m = g.m + (size_t)r * st3;
+    const real* k0 = g.k + (size_t)r * 7 * st3;
+    real* yn = ys1 + (size_t)r * st3;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) yn[d * n + i] = m[d * n + i] + ha * k0[d * n + i];
+  }
   group_sync(gs);
 
   int it = 0;
@@ -700,7 +829,7 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
           for (int d = 0; d < 3; ++d) P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 2) % 3) * 3 + d] = 0.0;
       const real* src = (s & 1) ? ys1 : ys0;
       real* dst = (s & 1) ? ys0 : ys1;
-      field_eval<real, kFixed, BS>(g, P, c, gs, i0, i1, s, src, dst, it, ev++, bL, RB, cs);
+      field_eval<real, kFixed, BS>(g, P, c, icL, gs, i0, i1, s, src, dst, it, ev++, bL, SL, RB, cs);
     }
     // ---- step decision per system (identical in every workgroup)
     for (int sl = threadIdx.x; sl < g.nsys; sl += BS) {
@@ -750,7 +879,7 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
       }
       c.prev_t[r] = t; c.prev_v[r] = vh;
       const bool save = (P.save_every > 0 && c.nacc[sl] % P.save_every == 0) || !c.active[sl];
-      if (lead && save) save_sample<real, BS>(g, P, c, r, t, c.h[sl], c.err[sl], ob);
+      if (lead && save) save_sample<real, BS>(g, P, c, icL, r, t, c.h[sl], c.err[sl], ob);
     }
     __syncthreads();
     // largest |1 - |y|| before renormalisation, over the instances of each accepted system
@@ -763,22 +892,38 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
         if (dev > c.maxdev[sl]) c.maxdev[sl] = dev;
       }
     }
-    // accepted: m <- y / |y| (the stage-7 input), k1 <- k7
-    for (int it2 = threadIdx.x; it2 < g.R * (i1 - i0); it2 += BS) {
-      const int r = it2 / (i1 - i0), i = i0 + (it2 - r * (i1 - i0));
-      const int sl = c.isys[r];
-      if (!c.accepted[sl]) continue;
-      real* m = g.m + (size_t)r * st3;
-      const real* y7 = ys0 + (size_t)r * st3;
-      real* k0 = g.k + (size_t)r * 7 * st3;
-      const real* k6 = k0 + 6 * st3;
-      const real a = y7[i], b = y7[n + i], d = y7[2 * n + i];
-      const real inv = (real)1 / sqrt(a * a + b * b + d * d);
-      m[i] = a * inv; m[n + i] = b * inv; m[2 * n + i] = d * inv;
-      k0[i] = k6[i]; k0[n + i] = k6[n + i]; k0[2 * n + i] = k6[2 * n + i];
-    }
+    plan_attempt<kFixed, BS>(P, c, g.nsys, nfix);
     __syncthreads();
-    begin_attempt<real, kFixed, BS>(g, P, c, i0, i1, ys1, nfix);
+    // accepted: m <- y / |y| (the stage-7 input), k1 <- k7; then the stage-2 input of the next
+    // attempt of every active system, from the values already in registers
+    for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
+      const int r = it2 / nown, i = i0 + (it2 - r * nown);
+      const int sl = c.isys[r];
+      const bool acc = c.accepted[sl], act = c.active[sl];
+      if (!acc && !act) continue;
+      real* m = g.m + (size_t)r * st3;
+      real* k0 = g.k + (size_t)r * 7 * st3;
+      real mv[3], kv[3];
+      if (acc) {
+        const real* y7 = ys0 + (size_t)r * st3;
+        const real* k6 = k0 + 6 * st3;
+        const real a = y7[i], b = y7[n + i], d = y7[2 * n + i];
+        kv[0] = k6[i]; kv[1] = k6[n + i]; kv[2] = k6[2 * n + i];
+        const real inv = (real)1 / sqrt(a * a + b * b + d * d);
+        mv[0] = a * inv; mv[1] = b * inv; mv[2] = d * inv;
+        m[i] = mv[0]; m[n + i] = mv[1]; m[2 * n + i] = mv[2];
+        k0[i] = kv[0]; k0[n + i] = kv[1]; k0[2 * n + i] = kv[2];
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { mv[d] = m[d * n + i]; kv[d] = k0[d * n + i]; }
+      }
+      if (act) {
+        const real ha = (real)(c.h[sl] * kA[1][0]);
+        real* yn = ys1 + (size_t)r * st3;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) yn[d * n + i] = mv[d] + ha * kv[d];
+      }
+    }
     group_sync(gs);
     ++it;
   }
@@ -886,26 +1031,22 @@ __global__ __launch_bounds__(256) void energy_kernel(const GroupView<real>* __re
 // ---------------------------------------------------------------------------------------------
 template <typename real>
 static const void* dp5_fn(bool fixed, int bs) {
-  if (bs == 1024)
-    return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 1024>)
-                 : reinterpret_cast<const void*>(&dp5_kernel<real, false, 1024>);
+  if (bs == 512)
+    return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 512>)
+                 : reinterpret_cast<const void*>(&dp5_kernel<real, false, 512>);
   return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 256>)
                : reinterpret_cast<const void*>(&dp5_kernel<real, false, 256>);
 }
 
-// LDS bytes of a CSR staging area of `cap` entries
 template <typename real>
-size_t csr_stage_bytes(int cap) {
-  return cap > 0 ? (size_t)cap * (7 * sizeof(real) + 2 * sizeof(int32_t)) + sizeof(int32_t) : 0;
-}
+size_t dp5_lds_bytes(const LdsPlan& L) { return lds_plan_bytes<real>(L); }
 
 template <typename real>
-hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int grid, int RB,
-                      int ldS_max, bool fixed, bool cooperative, hipStream_t stream, bool sym, int bs,
-                      int csr_cap) {
-  int bl_elems = (sym ? 2 : 1) * RB * ldS_max;
-  const size_t shm = (size_t)bl_elems * sizeof(real) + csr_stage_bytes<real>(csr_cap);
-  void* args[] = {(void*)&d_groups, (void*)&P, (void*)&RB, (void*)&bl_elems, (void*)&csr_cap};
+hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int grid, int RB, const LdsPlan& L,
+                      bool fixed, bool cooperative, hipStream_t stream, int bs) {
+  const size_t shm = lds_plan_bytes<real>(L);
+  LdsPlan Lc = L;
+  void* args[] = {(void*)&d_groups, (void*)&P, (void*)&RB, (void*)&Lc};
   const void* fn = dp5_fn<real>(fixed, bs);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
@@ -913,14 +1054,20 @@ hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int g
   return hipLaunchKernel(fn, dim3(grid), dim3(bs), args, shm, stream);
 }
 
+// resident workgroups per CU of the stepping kernel with this LDS plan (0 if it does not fit)
 template <typename real>
-hipError_t max_coresident(int RB, int ldS_max, bool fixed, int bs, int csr_cap, int* per_cu, int* cus) {
-  const size_t shm = (size_t)RB * ldS_max * sizeof(real) + csr_stage_bytes<real>(csr_cap);
+hipError_t max_coresident(const LdsPlan& L, bool fixed, int bs, int* per_cu, int* cus) {
+  const size_t shm = lds_plan_bytes<real>(L);
   const void* fn = dp5_fn<real>(fixed, bs);
+  *per_cu = 0;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, bs, shm);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    e = hipSuccess;
+  } else {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, bs, shm);
+    if (e != hipSuccess) return e;
+  }
   int dev;
   hipGetDevice(&dev);
   return hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -928,22 +1075,23 @@ hipError_t max_coresident(int RB, int ldS_max, bool fixed, int bs, int csr_cap, 
 
 template <typename real>
 hipError_t launch_energy(const GroupView<real>* d_groups, const int2* d_inst_map, int ninst,
-                         const RunParams& P, double* d_energy, int ldS_max, int nmax, hipStream_t stream) {
+                         const RunParams& P, double* d_energy, int nmax, hipStream_t stream) {
   const size_t shm = (size_t)nmax * sizeof(double);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&energy_kernel<real>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
-  (void)ldS_max;
   hipLaunchKernelGGL(energy_kernel<real>, dim3(ninst), dim3(kBlock), shm, stream, d_groups, d_inst_map,
                      P, d_energy);
   return hipGetLastError();
 }
 
-template hipError_t launch_dp5<float>(const GroupView<float>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool, int, int);
-template hipError_t launch_dp5<double>(const GroupView<double>*, const RunParams&, int, int, int, bool, bool, hipStream_t, bool, int, int);
-template hipError_t max_coresident<float>(int, int, bool, int, int, int*, int*);
-template hipError_t max_coresident<double>(int, int, bool, int, int, int*, int*);
-template hipError_t launch_energy<float>(const GroupView<float>*, const int2*, int, const RunParams&, double*, int, int, hipStream_t);
-template hipError_t launch_energy<double>(const GroupView<double>*, const int2*, int, const RunParams&, double*, int, int, hipStream_t);
+template size_t dp5_lds_bytes<float>(const LdsPlan&);
+template size_t dp5_lds_bytes<double>(const LdsPlan&);
+template hipError_t launch_dp5<float>(const GroupView<float>*, const RunParams&, int, int, const LdsPlan&, bool, bool, hipStream_t, int);
+template hipError_t launch_dp5<double>(const GroupView<double>*, const RunParams&, int, int, const LdsPlan&, bool, bool, hipStream_t, int);
+template hipError_t max_coresident<float>(const LdsPlan&, bool, int, int*, int*);
+template hipError_t max_coresident<double>(const LdsPlan&, bool, int, int*, int*);
+template hipError_t launch_energy<float>(const GroupView<float>*, const int2*, int, const RunParams&, double*, int, hipStream_t);
+template hipError_t launch_energy<double>(const GroupView<double>*, const int2*, int, const RunParams&, double*, int, hipStream_t);
 
 }  // namespace bpm

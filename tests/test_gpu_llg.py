@@ -102,16 +102,23 @@ def _run_gpu(ctx, mesh, S, mats, flds, *, offsets=None, coupled=False, m0=None, 
     return ms, res, trajs
 
 
-@pytest.mark.parametrize("wg", [1, 4])
-def test_fp64_fixed_step_trajectory_parity(ctx, cfg0, oracle_mod, wg):
-    """The single-island workload (1.2 T at 30 degrees, 0.1 ns ramp), DP5 at dt = 10 fs."""
+@pytest.mark.parametrize("wg,threads,s_in_lds", [(1, 256, False), (4, 256, False), (48, 256, True),
+                                                  (48, 512, True), (48, 256, False)])
+def test_fp64_fixed_step_trajectory_parity(ctx, cfg0, oracle_mod, wg, threads, s_in_lds):
+    """The single-island workload (1.2 T at 30 degrees, 0.1 ns ramp), DP5 at dt = 10 fs; one
+    workgroup, a few, and 48 workgroups whose rows of S stay in LDS (or are streamed)."""
+    from paper_1603_09493_amd import bpm
     mesh, mat, fld, om, S = cfg0
     T, dt = 0.05e-9, 10e-15
-    _print_case("fp64-fixed", n=mesh.n, wg=wg, steps=int(T / dt))
+    flags = (bpm.FLAG_WG512 if threads == 512 else 0) | (0 if s_in_lds else bpm.FLAG_STREAM_S)
+    _print_case("fp64-fixed", n=mesh.n, wg=wg, threads=threads, s_in_lds=s_in_lds, steps=int(T / dt))
     mo, ro, to = om.run(S, [mat], [fld], dict(t_end=T, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt,
                                               save_every=500), traj_cap=100)
     mg, rg, tg = _run_gpu(ctx, mesh, S, [mat], [fld], t_end=T, precision=64, integrator=1, dt_fixed=dt,
-                          save_every=500, traj_cap=100, wg_per_group=wg)
+                          save_every=500, traj_cap=100, wg_per_group=wg, flags=flags)
+    lay = ctx.last_run_layout()
+    assert lay["threads"] == threads
+    assert (lay["s_rows_lds"] > 0) == s_in_lds
     assert rg[0]["status"] == 0 and rg[0]["n_accept"] == ro[0]["n_accept"]
     assert np.abs(mg[0] - mo[0]).max() <= 1e-9
     # the trajectory moves: soft layer away from +z
@@ -181,11 +188,33 @@ def test_fp64_dipole_coupled_patch(ctx, oracle_mod):
     _print_case("fp64-patch", n=mesh.n)
     mo, ro, _ = om.run(S, mats, flds, dict(t_end=T, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt),
                        offsets=offs, coupled=True)
-    mg, rg, _ = _run_gpu(ctx, mesh, S, mats, flds, offsets=offs, coupled=True, t_end=T, precision=64,
-                         integrator=1, dt_fixed=dt, wg_per_group=2)
-    assert np.abs(mg - mo).max() <= 1e-9
-    for a, b in zip(rg, ro):
-        assert abs(a["energy"] - b["energy"]) <= 1e-9 * abs(b["energy"])
+    for wg in (2, 40):
+        mg, rg, _ = _run_gpu(ctx, mesh, S, mats, flds, offsets=offs, coupled=True, t_end=T, precision=64,
+                             integrator=1, dt_fixed=dt, wg_per_group=wg)
+        lay = ctx.last_run_layout()
+        assert (lay["s_rows_lds"] > 0) == (wg == 40), lay      # 40 workgroups: S rows in LDS
+        assert np.abs(mg - mo).max() <= 1e-9
+        for a, b in zip(rg, ro):
+            assert abs(a["energy"] - b["energy"]) <= 1e-9 * abs(b["energy"])
+
+
+def test_fp32_full_patch_resident_and_streamed_S_agree(ctx):
+    """Full-size patch (~2k nodes x 9 islands), FP32 fixed step: the launch with the rows of S
+    resident in LDS and the one streaming S from HBM take the same steps and agree to FP32
+    rounding (the summation order of the demag product is the same; only the source differs)."""
+    from paper_1603_09493_amd import bpm
+    mesh, mats, flds, offs = I.patch_workload()
+    T, dt = 0.002e-9, 5e-15
+    _print_case("fp32-patch-full", n=mesh.n)
+    out = {}
+    for name, flags in (("lds", 0), ("stream", bpm.FLAG_STREAM_S)):
+        mg, rg, _ = _run_gpu(ctx, mesh, None, mats, flds, offsets=offs, coupled=True, t_end=T, precision=32,
+                             integrator=1, dt_fixed=dt, wg_per_group=256, flags=flags)
+        lay = ctx.last_run_layout()
+        assert (lay["s_rows_lds"] > 0) == (name == "lds"), lay
+        assert all(r["status"] == 0 for r in rg)
+        out[name] = mg
+    assert np.array_equal(out["lds"], out["stream"])
 
 
 # ------------------------------------------------------------------------------------------
