@@ -42,7 +42,23 @@ __constant__ double kC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0}
 __constant__ double kE[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200,
                              22.0 / 525, -1.0 / 40};
 
-constexpr int kGather = 8;   // CSR entries whose gathers are issued together
+// CSR entries whose gathers are issued together (a whole row in FP32; FP64 halves it to stay in
+// registers)
+template <typename real> struct Gather { static constexpr int W = 24; };
+template <> struct Gather<double> { static constexpr int W = 12; };
+
+// Pointers loaded from memory (group views, launch parameters) are generic to the compiler; the
+// hot loops cast them to the global address space so that they compile to global_load/store,
+// which (unlike flat accesses) do not make every LDS wait also wait for outstanding HBM loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLB __attribute__((address_space(1)))
+#else
+#define GLB
+#endif
+template <typename T>
+__device__ __forceinline__ GLB T* glb(T* p) { return (GLB T*)p; }
+template <typename T>
+__device__ __forceinline__ const GLB T* glb(const T* p) { return (const GLB T*)p; }
 
 // ---------------------------------------------------------------------------------------------
 // small device helpers
@@ -76,8 +92,10 @@ __device__ __forceinline__ float vcomp(const float4& v, int q) {
 }
 __device__ __forceinline__ double vcomp(const double2& v, int q) { return q == 0 ? v.x : v.y; }
 
-// instances handled at once in the demag product, and vector loads per lane in flight
-template <int BS> struct PhaseBShape { static constexpr int RMAX = 16, U = 8; };
+// Demag product shape: instances handled at once, 16-byte loads per lane per row in flight, rows
+// per wave processed together (each staged right-hand-side vector read from LDS serves RW rows).
+template <typename real> struct PhaseBShape { static constexpr int RMAX = 16, U = 8, RW = 2; };
+template <> struct PhaseBShape<double> { static constexpr int RMAX = 16, U = 4, RW = 2; };
 
 struct GroupSync {
   unsigned long long* ctr;
@@ -151,22 +169,18 @@ struct Ctl {
 };
 
 // CSR rows and node data of the owned nodes [i0, i1), indexed by k = i - i0 (rp, pt, lay, V,
-// aif, x, y) or by the CSR position (col, K, D, DT): either global memory (rp = rowptr + i0,
-// node arrays offset by i0) or staged once into LDS (rp rebased to zero).  col holds the node
+// aif, x, y) or by the CSR position (col, K, D, DT): staged once into LDS (kL, rp rebased to zero)
+// or read from global memory (rp = rowptr + i0, node arrays offset by i0).  col holds the node
 // index in its low 16 bits and that node's layer above.
-template <typename real>
+template <typename real, bool kL>
 struct Csr {
-  const int32_t* rp;
-  const int32_t* col;
-  const real* K;
-  const real* D;
-  const real* DT;
-  const int32_t* pt;
-  const int32_t* lay;
-  const real* V;
-  const real* aif;
-  const double* x;
-  const double* y;
+  template <typename T>
+  using ptr = typename std::conditional<kL, const T*, const GLB T*>::type;
+  ptr<int32_t> rp, col;
+  ptr<real> K, D, DT;
+  ptr<int32_t> pt, lay;
+  ptr<real> V, aif;
+  ptr<double> x, y;
 };
 
 // LDS bytes of the staged CSR rows (cap entries) and node data (ocap nodes), 16-byte multiple
@@ -187,10 +201,10 @@ __host__ __device__ inline size_t lds_plan_bytes(const LdsPlan& L) {
          csr_stage_bytes<real>(L.csr_cap, L.own_cap) + (size_t)L.s_rows * L.ldS * sizeof(real);
 }
 
-// copy `cnt` 16-byte words, all loads of a thread in flight before its stores
-template <int BS>
-__device__ __forceinline__ void copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int cnt) {
-  constexpr int UN = 8;
+// copy `cnt` 16-byte words from global memory to LDS, UN loads of a thread in flight before its
+// stores
+template <int BS, int UN>
+__device__ __forceinline__ void copy16(uint4* __restrict__ dst, const GLB uint4* __restrict__ src, int cnt) {
   for (int base = threadIdx.x; base < cnt; base += BS * UN) {
     uint4 v[UN];
 #pragma unroll
@@ -209,10 +223,13 @@ __device__ __forceinline__ void copy16(uint4* __restrict__ dst, const uint4* __r
 // ---------------------------------------------------------------------------------------------
 // phase A: yex = K y, b = D (Ms y), dipole moments
 // ---------------------------------------------------------------------------------------------
-template <typename real, int BS>
+template <typename real, int BS, bool kL>
 __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
-                                        int i0, int i1, const real* __restrict__ ysrc, int ev, const Csr<real>& cs) {
+                                        int i0, int i1, const real* ysrc_, int ev, const Csr<real, kL>& cs) {
   const int n = g.n, nown = i1 - i0, ldS = g.ldS;
+  const GLB real* __restrict__ ysrc = glb(ysrc_);
+  GLB real* __restrict__ yexg = glb(g.yex);
+  GLB real* __restrict__ bg = glb(g.b);
   if (c.any_coupled) {
     for (int q = threadIdx.x; q < g.R * 3; q += BS) c.accL[q / 3][q % 3] = 0.0;
     __syncthreads();
@@ -222,10 +239,13 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
     const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
     if (!c.active[c.isys[r]]) continue;
     const real Ms0 = (real)icL[r].Ms[0], Ms1 = (real)icL[r].Ms[1];
-    const real* y = ysrc + (size_t)r * 3 * n;
+    const GLB real* y = ysrc + (size_t)r * 3 * n;
     real ex0 = 0, ex1 = 0, ex2 = 0, bb = 0;
     const int qa = cs.rp[k], qb = cs.rp[k + 1];
+    const real own0 = y[i], own1 = y[n + i], own2 = y[2 * n + i];
+    constexpr int kGather = Gather<real>::W;
     for (int q0 = qa; q0 < qb; q0 += kGather) {
+      // all gathers of the row in flight at once (masked entries read the node itself)
       int cj[kGather];
       real yx[kGather], yy[kGather], yz[kGather];
 #pragma unroll
@@ -248,16 +268,16 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
         }
       }
     }
-    real* yex = g.yex + (size_t)r * 3 * n;
+    GLB real* yex = yexg + (size_t)r * 3 * n;
     yex[i] = ex0;
     yex[n + i] = ex1;
     yex[2 * n + i] = ex2;
-    g.b[(size_t)r * ldS + i] = bb;
+    bg[(size_t)r * ldS + i] = bb;
     if (c.coupled[r]) {
       const double w = (double)(cs.lay[k] ? Ms1 : Ms0) * (double)cs.V[k];
-      atomicAdd(&c.accL[r][0], w * (double)y[i]);
-      atomicAdd(&c.accL[r][1], w * (double)y[n + i]);
-      atomicAdd(&c.accL[r][2], w * (double)y[2 * n + i]);
+      atomicAdd(&c.accL[r][0], w * (double)own0);
+      atomicAdd(&c.accL[r][1], w * (double)own1);
+      atomicAdd(&c.accL[r][2], w * (double)own2);
     }
   }
   if (c.any_coupled) {
@@ -273,6 +293,8 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
 // ---------------------------------------------------------------------------------------------
 // phase B: u = S b for the owned rows; b of up to RB instances staged in LDS.  kSL: the owned
 // rows of S are resident in LDS (SL, row k = node i0 + k), else they stream from global memory.
+// Each wave takes RW rows at a time; per row the sum over columns is per lane, then over the wave
+// (the same order for either source of S).
 // ---------------------------------------------------------------------------------------------
 template <typename real, int BS, bool kSL>
 __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* bL,
@@ -281,10 +303,16 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   constexpr int nw = BS / 64;
   constexpr int VEC = 16 / sizeof(real);
-  constexpr int U = PhaseBShape<BS>::U;           // vector loads per lane in flight per row chunk
-  constexpr int RMAX = PhaseBShape<BS>::RMAX;
+  constexpr int U = PhaseBShape<real>::U;         // 16-byte loads per lane and row in flight
+  constexpr int RMAX = PhaseBShape<real>::RMAX;
+  constexpr int RW = PhaseBShape<real>::RW;
   constexpr int STEP = 64 * VEC;                  // elements one wave covers per load
   using vec_t = typename std::conditional<sizeof(real) == 4, float4, double2>::type;
+  using sptr = typename std::conditional<kSL, const real*, const GLB real*>::type;
+  using vptr = typename std::conditional<kSL, const vec_t*, const GLB vec_t*>::type;
+  const sptr Sbase = kSL ? (sptr)SL : (sptr)(glb(g.S) + (size_t)i0 * ldS);
+  GLB real* __restrict__ ug = glb(g.u);
+  const int nr = i1 - i0;
   RB = min(RB, RMAX);
   for (int rb = 0; rb < g.R; rb += RB) {
     const int rn = min(RB, g.R - rb);
@@ -293,21 +321,28 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
     if (!any) continue;
     __syncthreads();
     // b rows are ldS long (zero padded), so the staging is one contiguous 16-byte copy
-    copy16<BS>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const uint4*>(g.b + (size_t)rb * ldS),
-               rn * ldS / VEC);
+    copy16<BS, 16>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
+                   rn * ldS / VEC);
     __syncthreads();
-    for (int row = i0 + wid; row < i1; row += nw) {
-      const real* Srow = kSL ? SL + (size_t)(row - i0) * ldS : g.S + (size_t)row * ldS;
-      real acc[RMAX];
+    for (int k0 = wid * RW; k0 < nr; k0 += nw * RW) {
+      sptr Srow[RW];
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) acc[r] = 0;
+      for (int w = 0; w < RW; ++w) Srow[w] = Sbase + (size_t)min(k0 + w, nr - 1) * ldS;
+      real acc[RW][RMAX];
+#pragma unroll
+      for (int w = 0; w < RW; ++w)
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) acc[w][r] = 0;
       for (int l0 = lane * VEC; l0 < ldS; l0 += STEP * U) {
-        vec_t sv[U];
+        vec_t sv[RW][U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int l = l0 + u * STEP;
-          if (l < ldS) sv[u] = *reinterpret_cast<const vec_t*>(Srow + l);
-          else sv[u] = vec_t{};
+#pragma unroll
+          for (int w = 0; w < RW; ++w) {
+            if (l < ldS) sv[w][u] = *reinterpret_cast<vptr>(Srow[w] + l);
+            else sv[w][u] = vec_t{};
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -318,16 +353,21 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
             if (r < rn) {
               const vec_t bv = *reinterpret_cast<const vec_t*>(bL + r * ldS + l);
 #pragma unroll
-              for (int q = 0; q < VEC; ++q) acc[r] += vcomp(sv[u], q) * vcomp(bv, q);
+              for (int w = 0; w < RW; ++w)
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) acc[w][r] += vcomp(sv[w][u], q) * vcomp(bv, q);
             }
           }
         }
       }
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) {
-        if (r < rn) {
-          const real v = wave_sum(acc[r]);
-          if (lane == 0) g.u[(size_t)(rb + r) * ldS + row] = v;
+      for (int w = 0; w < RW; ++w) {
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+          if (r < rn) {
+            const real v = wave_sum(acc[w][r]);
+            if (lane == 0 && k0 + w < nr) ug[(size_t)(rb + r) * ldS + i0 + k0 + w] = v;
+          }
         }
       }
     }
@@ -345,9 +385,11 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
   constexpr int nw = BS / 64;
   constexpr int VEC = 16 / sizeof(real);
   constexpr int U = 4;
-  constexpr int RMAX = PhaseBShape<BS>::RMAX;
+  constexpr int RMAX = PhaseBShape<real>::RMAX;
   constexpr int STEP = 64 * VEC;
   using vec_t = typename std::conditional<sizeof(real) == 4, float4, double2>::type;
+  const GLB real* Sg = glb(g.S);
+  GLB real* __restrict__ ug = glb(g.u);
   RB = min(RB, RMAX);
   real* uL = bL + (size_t)RB * ldS;
   for (int rb = 0; rb < g.R; rb += RB) {
@@ -356,12 +398,12 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
     for (int r = rb; r < rb + rn; ++r) any = any || c.active[c.isys[r]];
     if (!any) continue;
     __syncthreads();
-    copy16<BS>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const uint4*>(g.b + (size_t)rb * ldS),
-               rn * ldS / VEC);
+    copy16<BS, 16>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
+                   rn * ldS / VEC);
     for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) uL[idx] = (real)0;
     __syncthreads();
     for (int k = wid; k < n; k += nw) {
-      const real* Srow = g.S + (size_t)k * ldS;
+      const GLB real* Srow = Sg + (size_t)k * ldS;
       real acc[RMAX], bk[RMAX];
 #pragma unroll
       for (int r = 0; r < RMAX; ++r) {
@@ -374,7 +416,7 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int l = l0 + u * STEP;
-          if (l < ldS) sv[u] = *reinterpret_cast<const vec_t*>(Srow + l);
+          if (l < ldS) sv[u] = *reinterpret_cast<const GLB vec_t*>(Srow + l);
           else sv[u] = vec_t{};
         }
 #pragma unroll
@@ -407,44 +449,150 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
     __syncthreads();
     for (int idx = threadIdx.x; idx < rn * n; idx += BS) {
       const int r = idx / n, l = idx - r * n;
-      g.u[(size_t)(rb + r) * ldS + l] = uL[r * ldS + l];
+      ug[(size_t)(rb + r) * ldS + l] = uL[r * ldS + l];
     }
   }
-}
-
-// next stage input of stage S+1: m + sum_{l<S} (h a_{S+1,l}) k_l + (h a_{S+1,S}) k_S, with all
-// loads of the previous stages issued together
-template <typename real, int S>
-__device__ __forceinline__ void stage_input(const real* __restrict__ kr, const real* __restrict__ m, size_t st3,
-                                            int n, int i, double h, real kx, real ky, real kz, real* v) {
-  real kl[S > 0 ? S : 1][3];
-  real mm[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) mm[d] = m[d * n + i];
-#pragma unroll
-  for (int l = 0; l < S; ++l)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) kl[l][d] = kr[(size_t)l * st3 + d * n + i];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    real acc = 0;
-#pragma unroll
-    for (int l = 0; l < S; ++l) acc += (real)(h * kA[S + 1][l]) * kl[l][d];
-    v[d] = mm[d] + acc;
-  }
-  const real ha = (real)(h * kA[S + 1][S]);
-  v[0] += ha * kx; v[1] += ha * ky; v[2] += ha * kz;
 }
 
 // ---------------------------------------------------------------------------------------------
 // phase C: effective field, LLG right-hand side, next stage input, reductions
 // ---------------------------------------------------------------------------------------------
-template <typename real, bool kFixed, int BS>
-__device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
-                                        int i0, int i1, int s, const real* __restrict__ ysrc,
-                                        real* __restrict__ ydst, int it, int ev, const Csr<real>& cs) {
-  const int n = g.n, nown = i1 - i0, ldS = g.ldS;
+
+// One (instance r, node i = i0 + k) pair of stage s: every load the pair needs (own and partner
+// magnetisation, exchange sums, potentials of the CSR row, m and the earlier stages) is issued
+// before the arithmetic that consumes it.  s is uniform over the workgroup, so the loads of the
+// stages below s are predicated by scalar branches and stay in flight together.
+template <typename real, bool kL>
+__device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst& ic,
+                                       int s, int r, int k, int i0, int sl, const GLB real* __restrict__ ysrc,
+                                       GLB real* __restrict__ ydst, const Csr<real, kL>& cs) {
+  const int nk = s < 6 ? s : 6;     // earlier stages read
+  const int n = g.n, ldS = g.ldS, i = i0 + k;
   const size_t st3 = (size_t)3 * n;
+  const double h = c.h[sl];
+  const double ts = c.t[sl] + kC[s] * h;
+  const GLB real* y = ysrc + (size_t)r * st3;
+  const GLB real* yex = glb(g.yex) + (size_t)r * st3;
+  const GLB real* u = glb(g.u) + (size_t)r * ldS;
+  GLB real* kr = glb(g.k) + (size_t)r * 7 * st3;
+  const GLB real* m = glb(g.m) + (size_t)r * st3;
+  GLB real* yn = ydst + (size_t)r * st3;
+  const int L = cs.lay[k];
+  const real Vi = cs.V[k];
+  const int p = cs.pt[k];
+  const int pp = p >= 0 ? p : i;
+  // loads
+  const real mx = y[i], my = y[n + i], mz = y[2 * n + i];
+  const real ex0 = yex[i], ex1 = yex[n + i], ex2 = yex[2 * n + i];
+  const real px = y[pp], py = y[n + pp], pz = y[2 * n + pp];
+  real mm[3], kl[6][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) mm[d] = m[d * n + i];
+#pragma unroll
+  for (int l = 0; l < 6; ++l)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) kl[l][d] = l < nk ? kr[(size_t)l * st3 + d * n + i] : (real)0;
+  // demag: -mu0 / V_i (D^T u)_i
+  real dx = 0, dy = 0, dz = 0;
+  const int qa = cs.rp[k], qb = cs.rp[k + 1];
+  constexpr int kGather = Gather<real>::W;
+  for (int q0 = qa; q0 < qb; q0 += kGather) {
+    real uq[kGather];
+#pragma unroll
+    for (int w = 0; w < kGather; ++w) uq[w] = u[q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i];
+#pragma unroll
+    for (int w = 0; w < kGather; ++w) {
+      const int q = q0 + w;
+      if (q < qb) {
+        dx += cs.DT[3 * q] * uq[w];
+        dy += cs.DT[3 * q + 1] * uq[w];
+        dz += cs.DT[3 * q + 2] * uq[w];
+      }
+    }
+  }
+  const real gp = (real)ic.gp, al = (real)ic.alpha;
+  // exchange
+  const real cex = -(real)ic.cex[L] / Vi;
+  real Bx = cex * ex0, By = cex * ex1, Bz = cex * ex2;
+  // anisotropy
+  const real ux = (real)ic.axis[L][0], uy = (real)ic.axis[L][1], uz = (real)ic.axis[L][2];
+  const real mu = (real)ic.can[L] * (mx * ux + my * uy + mz * uz);
+  Bx += mu * ux; By += mu * uy; Bz += mu * uz;
+  // interlayer
+  if (p >= 0) {
+    const real ci = (real)ic.cint[L] * cs.aif[k] / Vi;
+    Bx += ci * px; By += ci * py; Bz += ci * pz;
+  }
+  const real cd = -(real)kMu0 / Vi;
+  Bx += cd * dx; By += cd * dy; Bz += cd * dz;
+  // Zeeman (+ dipoles)
+  double zx, zy, zz;
+  applied_B(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
+  if (c.coupled[r]) { zx += c.Bdip[r][0]; zy += c.Bdip[r][1]; zz += c.Bdip[r][2]; }
+  Bx += (real)zx; By += (real)zy; Bz += (real)zz;
+  // LLG: dm/dt = -gp [ m x B + alpha m x (m x B) ]
+  const real cx = my * Bz - mz * By, cy = mz * Bx - mx * Bz, cz = mx * By - my * Bx;
+  const real dx2 = my * cz - mz * cy, dy2 = mz * cx - mx * cz, dz2 = mx * cy - my * cx;
+  const real kx = -gp * (cx + al * dx2), ky = -gp * (cy + al * dy2), kz = -gp * (cz + al * dz2);
+  GLB real* ks = kr + (size_t)s * st3;
+  ks[i] = kx; ks[n + i] = ky; ks[2 * n + i] = kz;
+  if (s < 6) {
+    // next stage input m + h sum_l a_{s+1,l} k_l (stage 7 input = 5th-order solution)
+    real v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      real acc = 0;
+#pragma unroll
+      for (int l = 0; l < 6; ++l)
+        if (l < nk) acc += (real)(h * kA[s + 1][l]) * kl[l][d];
+      v[d] = mm[d] + acc;
+    }
+    const real ha = (real)(h * kA[s + 1][s]);
+    v[0] += ha * kx; v[1] += ha * ky; v[2] += ha * kz;
+    yn[i] = v[0]; yn[n + i] = v[1]; yn[2 * n + i] = v[2];
+    if (s == 5) {
+      // observables of the normalised candidate
+      const double nr = sqrt((double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2]);
+      const double Ms = ic.Ms[L], Vd = (double)Vi;
+      const double nz = (double)v[2] / nr;
+      atomicAdd(&c.accL[r][L ? 1 : 0], Vd * nz);
+      atomicAdd(&c.accL[r][2], Ms * Vd * (double)v[0] / nr);
+      atomicAdd(&c.accL[r][3], Ms * Vd * (double)v[1] / nr);
+      atomicAdd(&c.accL[r][4], Ms * Vd * nz);
+      atomicMax(reinterpret_cast<unsigned long long*>(&c.accL[r][5]),
+                (unsigned long long)__double_as_longlong(fabs(1.0 - nr)));
+    }
+  } else {
+    // error estimate h sum_l e_l k_l, scaled per component
+    const real rtol = (real)P.rtol, atol = (real)P.atol;
+    real e[3] = {0, 0, 0};
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      const real he = (real)(h * kE[l]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) e[d] += he * kl[l][d];
+    }
+    const real he6 = (real)(h * kE[6]);
+    e[0] += he6 * kx; e[1] += he6 * ky; e[2] += he6 * kz;
+    const real y1[3] = {mx, my, mz};
+    double es = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const real sc = atol + rtol * fmax(fabs(mm[d]), fabs(y1[d]));
+      const real qq = e[d] / sc;
+      es += (double)(qq * qq);
+    }
+    atomicAdd(&c.errL[sl], es);
+  }
+}
+
+template <typename real, bool kFixed, int BS, bool kL>
+__device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
+                                        int i0, int i1, int s, const real* ysrc_, real* ydst_, int it, int ev,
+                                        const Csr<real, kL>& cs) {
+  const int nown = i1 - i0;
+  const GLB real* ysrc = glb(ysrc_);
+  GLB real* ydst = glb(ydst_);
   // dipole fields of coupled instances from the moments of this stage
   if (c.any_coupled) {
     for (int q = threadIdx.x; q < g.R * 3; q += BS)
@@ -476,121 +624,11 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
     for (int q = threadIdx.x; q < g.nsys; q += BS) c.errL[q] = 0.0;
   }
   __syncthreads();
-  const real rtol = (real)P.rtol, atol = (real)P.atol;
   for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
-    const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
+    const int r = it2 / nown, k = it2 - r * nown;
     const int sl = c.isys[r];
     if (!c.active[sl]) continue;
-    const InstConst& ic = icL[r];
-    const double h = c.h[sl];
-    const double ts = c.t[sl] + kC[s] * h;
-    const real* y = ysrc + (size_t)r * st3;
-    const real* yex = g.yex + (size_t)r * st3;
-    const real* u = g.u + (size_t)r * ldS;
-    real* kr = g.k + (size_t)r * 7 * st3;
-    const real* m = g.m + (size_t)r * st3;
-    real* yn = ydst + (size_t)r * st3;
-    const real gp = (real)ic.gp, al = (real)ic.alpha;
-    const int L = cs.lay[k];
-    const real Vi = cs.V[k];
-    const int p = cs.pt[k];
-    const real mx = y[i], my = y[n + i], mz = y[2 * n + i];
-    const real ex0 = yex[i], ex1 = yex[n + i], ex2 = yex[2 * n + i];
-    const int pp = p >= 0 ? p : i;
-    const real px = y[pp], py = y[n + pp], pz = y[2 * n + pp];
-    // demag: -mu0 / V_i (D^T u)_i, gathers of u issued in batches
-    real dx = 0, dy = 0, dz = 0;
-    const int qa = cs.rp[k], qb = cs.rp[k + 1];
-    for (int q0 = qa; q0 < qb; q0 += kGather) {
-      real uq[kGather];
-#pragma unroll
-      for (int w = 0; w < kGather; ++w) uq[w] = u[q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i];
-#pragma unroll
-      for (int w = 0; w < kGather; ++w) {
-        const int q = q0 + w;
-        if (q < qb) {
-          dx += cs.DT[3 * q] * uq[w];
-          dy += cs.DT[3 * q + 1] * uq[w];
-          dz += cs.DT[3 * q + 2] * uq[w];
-        }
-      }
-    }
-    // exchange
-    const real cex = -(real)ic.cex[L] / Vi;
-    real Bx = cex * ex0, By = cex * ex1, Bz = cex * ex2;
-    // anisotropy
-    const real ux = (real)ic.axis[L][0], uy = (real)ic.axis[L][1], uz = (real)ic.axis[L][2];
-    const real mu = (real)ic.can[L] * (mx * ux + my * uy + mz * uz);
-    Bx += mu * ux; By += mu * uy; Bz += mu * uz;
-    // interlayer
-    if (p >= 0) {
-      const real ci = (real)ic.cint[L] * cs.aif[k] / Vi;
-      Bx += ci * px; By += ci * py; Bz += ci * pz;
-    }
-    const real cd = -(real)kMu0 / Vi;
-    Bx += cd * dx; By += cd * dy; Bz += cd * dz;
-    // Zeeman (+ dipoles)
-    double zx, zy, zz;
-    applied_B(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
-    if (c.coupled[r]) { zx += c.Bdip[r][0]; zy += c.Bdip[r][1]; zz += c.Bdip[r][2]; }
-    Bx += (real)zx; By += (real)zy; Bz += (real)zz;
-    // LLG: dm/dt = -gp [ m x B + alpha m x (m x B) ]
-    const real cx = my * Bz - mz * By, cy = mz * Bx - mx * Bz, cz = mx * By - my * Bx;
-    const real dx2 = my * cz - mz * cy, dy2 = mz * cx - mx * cz, dz2 = mx * cy - my * cx;
-    const real kx = -gp * (cx + al * dx2), ky = -gp * (cy + al * dy2), kz = -gp * (cz + al * dz2);
-    real* ks = kr + (size_t)s * st3;
-    ks[i] = kx; ks[n + i] = ky; ks[2 * n + i] = kz;
-    if (s < 6) {
-      // next stage input m + h sum_l a_{s+1,l} k_l (stage 7 input = 5th-order solution)
-      real v[3];
-      switch (s) {
-        case 0: stage_input<real, 0>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
-        case 1: stage_input<real, 1>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
-        case 2: stage_input<real, 2>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
-        case 3: stage_input<real, 3>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
-        case 4: stage_input<real, 4>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
-        default: stage_input<real, 5>(kr, m, st3, n, i, h, kx, ky, kz, v); break;
-      }
-      yn[i] = v[0]; yn[n + i] = v[1]; yn[2 * n + i] = v[2];
-      if (s == 5) {
-        // observables of the normalised candidate
-        const double nr = sqrt((double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2]);
-        const double Ms = ic.Ms[L], Vd = (double)Vi;
-        const double nz = (double)v[2] / nr;
-        atomicAdd(&c.accL[r][L ? 1 : 0], Vd * nz);
-        atomicAdd(&c.accL[r][2], Ms * Vd * (double)v[0] / nr);
-        atomicAdd(&c.accL[r][3], Ms * Vd * (double)v[1] / nr);
-        atomicAdd(&c.accL[r][4], Ms * Vd * nz);
-        atomicMax(reinterpret_cast<unsigned long long*>(&c.accL[r][5]),
-                  (unsigned long long)__double_as_longlong(fabs(1.0 - nr)));
-      }
-    } else {
-      // error estimate h sum_l e_l k_l, scaled per component
-      real kl[6][3];
-#pragma unroll
-      for (int l = 0; l < 6; ++l)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) kl[l][d] = kr[(size_t)l * st3 + d * n + i];
-      const real y0[3] = {m[i], m[n + i], m[2 * n + i]};
-      real e[3] = {0, 0, 0};
-#pragma unroll
-      for (int l = 0; l < 6; ++l) {
-        const real he = (real)(h * kE[l]);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) e[d] += he * kl[l][d];
-      }
-      const real he6 = (real)(h * kE[6]);
-      e[0] += he6 * kx; e[1] += he6 * ky; e[2] += he6 * kz;
-      const real y1[3] = {mx, my, mz};
-      double es = 0.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const real sc = atol + rtol * fmax(fabs(y0[d]), fabs(y1[d]));
-        const real qq = e[d] / sc;
-        es += (double)(qq * qq);
-      }
-      atomicAdd(&c.errL[sl], es);
-    }
+    pair_C<real, kL>(g, P, c, icL[r], s, r, k, i0, sl, ysrc, ydst, cs);
   }
   if (s >= 5) {
     __syncthreads();
@@ -610,17 +648,17 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
   }
 }
 
-template <typename real, bool kFixed, int BS>
+template <typename real, bool kFixed, int BS, bool kL>
 __device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
                                            GroupSync& gs, int i0, int i1, int s, const real* ysrc, real* ydst,
-                                           int it, int ev, real* bL, const real* SL, int RB, const Csr<real>& cs) {
-  phase_A<real, BS>(g, P, c, icL, i0, i1, ysrc, ev, cs);
+                                           int it, int ev, real* bL, const real* SL, int RB, const Csr<real, kL>& cs) {
+  phase_A<real, BS, kL>(g, P, c, icL, i0, i1, ysrc, ev, cs);
   group_sync(gs);
   if (SL) phase_B<real, BS, true>(g, c, i0, i1, bL, SL, RB);
   else if (g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real, BS>(g, c, bL, RB);
   else phase_B<real, BS, false>(g, c, i0, i1, bL, nullptr, RB);
   group_sync(gs);
-  phase_C<real, kFixed, BS>(g, P, c, icL, i0, i1, s, ysrc, ydst, it, ev, cs);
+  phase_C<real, kFixed, BS, kL>(g, P, c, icL, i0, i1, s, ysrc, ydst, it, ev, cs);
   group_sync(gs);
 }
 
@@ -667,72 +705,18 @@ __device__ __forceinline__ void plan_attempt(const RunParams& P, Ctl& c, int nsy
   }
 }
 
-template <typename real, bool kFixed, int BS>
-__global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restrict__ groups,
-                                                 RunParams P, int RB, LdsPlan LP) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ Ctl c;
-  const int2 gm = P.wg_map[blockIdx.x];
-  const GroupView<real> g = groups[gm.x];
-  const int w = gm.y;
-  const int n = g.n, ldS = g.ldS;
+template <typename real, bool kFixed, int BS, bool kL>
+__device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
+                                         int w, real* bL, const real* SL, int RB, const Csr<real, kL>& cs) {
+  const int n = g.n;
   const int i0 = (int)((long long)n * w / g.G), i1 = (int)((long long)n * (w + 1) / g.G);
   const int nown = i1 - i0;
   const size_t st3 = (size_t)3 * n;
   const size_t ybuf = (size_t)g.R * st3;
   GroupSync gs{g.bar, 0ull, g.G};
   const bool lead = (w == 0);
-  // ---- dynamic LDS: instance constants, staged right-hand sides, CSR rows, S rows
-  unsigned char* lp = smem_raw;
-  InstConst* icL = reinterpret_cast<InstConst*>(lp);
-  lp += ic_stage_bytes(LP.ic_slots);
-  real* bL = reinterpret_cast<real*>(lp);
-  lp += ((size_t)LP.bl_elems * sizeof(real) + 15) / 16 * 16;
-  unsigned char* csr_lds = lp;
-  lp += csr_stage_bytes<real>(LP.csr_cap, LP.own_cap);
-  // S rows are resident only when this workgroup's rows fit the planned area
-  real* SL = (LP.s_rows > 0 && nown <= LP.s_rows) ? reinterpret_cast<real*>(lp) : nullptr;
-  copy16<BS>(reinterpret_cast<uint4*>(icL), reinterpret_cast<const uint4*>(P.inst + g.inst0),
-             (int)(g.R * sizeof(InstConst) / 16));
-  if (SL) {
-    // the owned rows of S, once for the whole launch
-    constexpr int VEC = 16 / sizeof(real);
-    copy16<BS>(reinterpret_cast<uint4*>(SL), reinterpret_cast<const uint4*>(g.S + (size_t)i0 * ldS), nown * ldS / VEC);
-  }
-  Csr<real> cs{g.rowptr + i0, g.colx, g.K, g.D, g.DT, g.partner + i0, g.layer + i0, g.V + i0, g.aif + i0, g.x + i0, g.y + i0};
-  {
-    const int q0 = g.rowptr[i0], nq = g.rowptr[i1] - q0;
-    if (LP.csr_cap > 0 && nq <= LP.csr_cap && nown <= LP.own_cap) {
-      const int cap = LP.csr_cap, ocap = LP.own_cap;
-      double* xL = reinterpret_cast<double*>(csr_lds);
-      double* yL = xL + ocap;
-      real* KL = reinterpret_cast<real*>(yL + ocap);
-      real* DL = KL + cap;
-      real* DTL = DL + 3 * cap;
-      real* VL = DTL + 3 * cap;
-      real* aL = VL + ocap;
-      int32_t* colL = reinterpret_cast<int32_t*>(aL + ocap);
-      int32_t* rpL = colL + cap;
-      int32_t* ptL = rpL + ocap + 1;
-      int32_t* layL = ptL + ocap;
-      for (int q = threadIdx.x; q < nq; q += BS) {
-        colL[q] = g.colx[q0 + q];
-        KL[q] = g.K[q0 + q];
-        for (int d = 0; d < 3; ++d) {
-          DL[3 * q + d] = g.D[3 * (q0 + q) + d];
-          DTL[3 * q + d] = g.DT[3 * (q0 + q) + d];
-        }
-      }
-      for (int k = threadIdx.x; k <= nown; k += BS) rpL[k] = g.rowptr[i0 + k] - q0;
-      for (int k = threadIdx.x; k < nown; k += BS) {
-        ptL[k] = g.partner[i0 + k]; layL[k] = g.layer[i0 + k];
-        VL[k] = g.V[i0 + k]; aL[k] = g.aif[i0 + k];
-        xL[k] = g.x[i0 + k]; yL[k] = g.y[i0 + k];
-      }
-      cs = Csr<real>{rpL, colL, KL, DL, DTL, ptL, layL, VL, aL, xL, yL};
-    }
-  }
-  __syncthreads();
+  GLB real* __restrict__ mg = glb(g.m);
+  GLB real* __restrict__ kg = glb(g.k);
   const long long nfix = kFixed ? (long long)ceil(P.t_end / P.dt_fixed - 1e-9) : 0;
 
   // ---- init control state
@@ -767,9 +751,10 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
     const int L = cs.lay[k];
     const double Vd = (double)cs.V[k], Ms = ic.Ms[L];
     real v[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      v[d] = g.m[(size_t)r * st3 + d * n + i];
-      ys0[(size_t)r * st3 + d * n + i] = v[d];
+      v[d] = mg[(size_t)r * st3 + d * n + i];
+      glb(ys0)[(size_t)r * st3 + d * n + i] = v[d];
     }
     atomicAdd(&c.accL[r][L ? 1 : 0], Vd * (double)v[2]);
     atomicAdd(&c.accL[r][2], Ms * Vd * (double)v[0]);
@@ -780,57 +765,67 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
   for (int q = threadIdx.x; q < g.R * 5; q += BS)
     atomicAdd(&P.obs_acc[((size_t)(g.inst0 + q / 5) * 3 + 2) * 6 + q % 5], c.accL[q / 5][q % 5]);
   group_sync(gs);
-  int ev = 0;
-  field_eval<real, kFixed, BS>(g, P, c, icL, gs, i0, i1, 0, ys0, ys1, 2, ev++, bL, SL, RB, cs);
-  // initial observables, crossing state, first trajectory sample
-  for (int r = threadIdx.x; r < g.R; r += BS) {
-    const double* ob = &P.obs_acc[((size_t)(g.inst0 + r) * 3 + 2) * 6];
-    const double vh = g.Vhard > 0 ? ob[1] / g.Vhard : 0.0;
-    c.prev_t[r] = 0.0; c.prev_v[r] = vh;
-    c.mzs[r] = g.Vsoft > 0 ? ob[0] / g.Vsoft : 0.0; c.mzh[r] = vh;
-    if (vh <= 0.0) { c.crossed[r] = 1; c.tsw[r] = 0.0; }
-    if (lead) save_sample<real, BS>(g, P, c, icL, r, 0.0, 0.0, 0.0, ob);
-  }
-  __syncthreads();
-  plan_attempt<kFixed, BS>(P, c, g.nsys, nfix);
-  __syncthreads();
-  for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
-    const int r = it2 / nown, i = i0 + (it2 - r * nown);
-    const int sl = c.isys[r];
-    if (!c.active[sl]) continue;
-    const real ha = (real)(c.h[sl] * kA[1][0]);
-    const real* m = g.m + (size_t)r * st3;
-    const real* k0 = g.k + (size_t)r * 7 * st3;
-    real* yn = ys1 + (size_t)r * st3;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) yn[d * n + i] = m[d * n + i] + ha * k0[d * n + i];
-  }
-  group_sync(gs);
-
-  int it = 0;
+  // One call site of the field evaluation (its code is large): the evaluation of stage 0 of the
+  // prologue is the first pass of the loop, then stages 1..6 of every attempt.
+  int ev = 0, it = 0, s = 0;
   for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int a = 0;
-      for (int sl = 0; sl < g.nsys; ++sl) a |= c.active[sl];
-      c.any_active = a;
-    }
-    __syncthreads();
-    if (!c.any_active) break;
-    // clear the accumulators used two attempts ago (every workgroup has read them)
-    if (lead) {
-      for (int r = threadIdx.x; r < g.R; r += BS)
-        for (int d = 0; d < 6; ++d) P.obs_acc[((size_t)(g.inst0 + r) * 3 + (it + 2) % 3) * 6 + d] = 0.0;
-      for (int sl = threadIdx.x; sl < g.nsys; sl += BS) P.err_acc[(size_t)(g.sys0 + sl) * 3 + (it + 2) % 3] = 0.0;
-    }
-    for (int s = 1; s < 7; ++s) {
-      if (lead && c.any_coupled)
+    if (s == 1) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int a = 0;
+        for (int sl = 0; sl < g.nsys; ++sl) a |= c.active[sl];
+        c.any_active = a;
+      }
+      __syncthreads();
+      if (!c.any_active) break;
+      // clear the accumulators used two attempts ago (every workgroup has read them)
+      if (lead) {
         for (int r = threadIdx.x; r < g.R; r += BS)
-          for (int d = 0; d < 3; ++d) P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 2) % 3) * 3 + d] = 0.0;
+          for (int d = 0; d < 6; ++d) P.obs_acc[((size_t)(g.inst0 + r) * 3 + (it + 2) % 3) * 6 + d] = 0.0;
+        for (int sl = threadIdx.x; sl < g.nsys; sl += BS) P.err_acc[(size_t)(g.sys0 + sl) * 3 + (it + 2) % 3] = 0.0;
+      }
+    }
+    if (s >= 1 && lead && c.any_coupled)
+      for (int r = threadIdx.x; r < g.R; r += BS)
+        for (int d = 0; d < 3; ++d) P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 2) % 3) * 3 + d] = 0.0;
+    {
       const real* src = (s & 1) ? ys1 : ys0;
       real* dst = (s & 1) ? ys0 : ys1;
-      field_eval<real, kFixed, BS>(g, P, c, icL, gs, i0, i1, s, src, dst, it, ev++, bL, SL, RB, cs);
+      field_eval<real, kFixed, BS, kL>(g, P, c, icL, gs, i0, i1, s, src, dst, it, ev++, bL, SL, RB, cs);
     }
+    if (s == 0) {
+      // initial observables, crossing state, first trajectory sample
+      for (int r = threadIdx.x; r < g.R; r += BS) {
+        const double* ob = &P.obs_acc[((size_t)(g.inst0 + r) * 3 + 2) * 6];
+        const double vh = g.Vhard > 0 ? ob[1] / g.Vhard : 0.0;
+        c.prev_t[r] = 0.0; c.prev_v[r] = vh;
+        c.mzs[r] = g.Vsoft > 0 ? ob[0] / g.Vsoft : 0.0; c.mzh[r] = vh;
+        if (vh <= 0.0) { c.crossed[r] = 1; c.tsw[r] = 0.0; }
+        if (lead) save_sample<real, BS>(g, P, c, icL, r, 0.0, 0.0, 0.0, ob);
+      }
+      __syncthreads();
+      plan_attempt<kFixed, BS>(P, c, g.nsys, nfix);
+      __syncthreads();
+      for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
+        const int r = it2 / nown, i = i0 + (it2 - r * nown);
+        const int sl = c.isys[r];
+        if (!c.active[sl]) continue;
+        const real ha = (real)(c.h[sl] * kA[1][0]);
+        const GLB real* m = mg + (size_t)r * st3;
+        const GLB real* k0 = kg + (size_t)r * 7 * st3;
+        GLB real* yn = glb(ys1) + (size_t)r * st3;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) yn[d * n + i] = m[d * n + i] + ha * k0[d * n + i];
+      }
+      group_sync(gs);
+      s = 1;
+      continue;
+    }
+    if (s < 6) {
+      ++s;
+      continue;
+    }
+    s = 1;
     // ---- step decision per system (identical in every workgroup)
     for (int sl = threadIdx.x; sl < g.nsys; sl += BS) {
       c.accepted[sl] = 0;
@@ -901,12 +896,12 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
       const int sl = c.isys[r];
       const bool acc = c.accepted[sl], act = c.active[sl];
       if (!acc && !act) continue;
-      real* m = g.m + (size_t)r * st3;
-      real* k0 = g.k + (size_t)r * 7 * st3;
+      GLB real* m = mg + (size_t)r * st3;
+      GLB real* k0 = kg + (size_t)r * 7 * st3;
       real mv[3], kv[3];
       if (acc) {
-        const real* y7 = ys0 + (size_t)r * st3;
-        const real* k6 = k0 + 6 * st3;
+        const GLB real* y7 = glb(ys0) + (size_t)r * st3;
+        const GLB real* k6 = k0 + 6 * st3;
         const real a = y7[i], b = y7[n + i], d = y7[2 * n + i];
         kv[0] = k6[i]; kv[1] = k6[n + i]; kv[2] = k6[2 * n + i];
         const real inv = (real)1 / sqrt(a * a + b * b + d * d);
@@ -919,7 +914,7 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
       }
       if (act) {
         const real ha = (real)(c.h[sl] * kA[1][0]);
-        real* yn = ys1 + (size_t)r * st3;
+        GLB real* yn = glb(ys1) + (size_t)r * st3;
 #pragma unroll
         for (int d = 0; d < 3; ++d) yn[d * n + i] = mv[d] + ha * kv[d];
       }
@@ -939,6 +934,83 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
       o.crossed = c.crossed[r]; o.t_sw = c.tsw[r]; o.mz_soft = c.mzs[r]; o.mz_hard = c.mzh[r];
       o.switched = c.mzh[r] < 0.0; o.n_traj = c.ntraj[r];
     }
+  }
+}
+
+
+template <typename real, bool kFixed, int BS, bool kL>
+__global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restrict__ groups,
+                                                 RunParams P, int RB, LdsPlan LP) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ Ctl c;
+  const int2 gm = P.wg_map[blockIdx.x];
+  const GroupView<real> g = groups[gm.x];
+  const int w = gm.y;
+  const int n = g.n, ldS = g.ldS;
+  const int i0 = (int)((long long)n * w / g.G), i1 = (int)((long long)n * (w + 1) / g.G);
+  const int nown = i1 - i0;
+  // ---- dynamic LDS: instance constants, staged right-hand sides, CSR rows, S rows
+  unsigned char* lp = smem_raw;
+  InstConst* icL = reinterpret_cast<InstConst*>(lp);
+  lp += ic_stage_bytes(LP.ic_slots);
+  real* bL = reinterpret_cast<real*>(lp);
+  lp += ((size_t)LP.bl_elems * sizeof(real) + 15) / 16 * 16;
+  unsigned char* csr_lds = lp;
+  lp += csr_stage_bytes<real>(LP.csr_cap, LP.own_cap);
+  // S rows are resident only when this workgroup's rows fit the planned area
+  real* SL = (LP.s_rows > 0 && nown <= LP.s_rows) ? reinterpret_cast<real*>(lp) : nullptr;
+  copy16<BS, 4>(reinterpret_cast<uint4*>(icL), reinterpret_cast<const GLB uint4*>(glb(P.inst + g.inst0)),
+                (int)(g.R * sizeof(InstConst) / 16));
+  if (SL) {
+    // the owned rows of S, once for the whole launch
+    constexpr int VEC = 16 / sizeof(real);
+    copy16<BS, 8>(reinterpret_cast<uint4*>(SL), reinterpret_cast<const GLB uint4*>(glb(g.S) + (size_t)i0 * ldS),
+                  nown * ldS / VEC);
+  }
+  if constexpr (kL) {
+    // CSR rows and node data of the owned nodes, once for the whole launch (the launch plan sizes
+    // csr_cap and own_cap for the largest workgroup share; the copies are clamped to them)
+    const int cap = LP.csr_cap, ocap = LP.own_cap;
+    const int q0 = g.rowptr[i0], nq = min(g.rowptr[i1] - q0, cap), no = min(nown, ocap);
+    double* xL = reinterpret_cast<double*>(csr_lds);
+    double* yL = xL + ocap;
+    real* KL = reinterpret_cast<real*>(yL + ocap);
+    real* DL = KL + cap;
+    real* DTL = DL + 3 * cap;
+    real* VL = DTL + 3 * cap;
+    real* aL = VL + ocap;
+    int32_t* colL = reinterpret_cast<int32_t*>(aL + ocap);
+    int32_t* rpL = colL + cap;
+    int32_t* ptL = rpL + ocap + 1;
+    int32_t* layL = ptL + ocap;
+    const GLB int32_t* colx = glb(g.colx);
+    const GLB real* Kg = glb(g.K);
+    const GLB real* Dg = glb(g.D);
+    const GLB real* DTg = glb(g.DT);
+    for (int q = threadIdx.x; q < nq; q += BS) {
+      colL[q] = colx[q0 + q];
+      KL[q] = Kg[q0 + q];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        DL[3 * q + d] = Dg[3 * (q0 + q) + d];
+        DTL[3 * q + d] = DTg[3 * (q0 + q) + d];
+      }
+    }
+    for (int k = threadIdx.x; k <= no; k += BS) rpL[k] = min(g.rowptr[i0 + k] - q0, nq);
+    for (int k = threadIdx.x; k < no; k += BS) {
+      ptL[k] = g.partner[i0 + k]; layL[k] = g.layer[i0 + k];
+      VL[k] = g.V[i0 + k]; aL[k] = g.aif[i0 + k];
+      xL[k] = g.x[i0 + k]; yL[k] = g.y[i0 + k];
+    }
+    const Csr<real, true> cs{rpL, colL, KL, DL, DTL, ptL, layL, VL, aL, xL, yL};
+    __syncthreads();
+    dp5_body<real, kFixed, BS, true>(g, P, c, icL, w, bL, SL, RB, cs);
+  } else {
+    const Csr<real, false> cs{glb(g.rowptr) + i0, glb(g.colx), glb(g.K), glb(g.D), glb(g.DT),
+                              glb(g.partner) + i0, glb(g.layer) + i0, glb(g.V) + i0, glb(g.aif) + i0,
+                              glb(g.x) + i0, glb(g.y) + i0};
+    __syncthreads();
+    dp5_body<real, kFixed, BS, false>(g, P, c, icL, w, bL, SL, RB, cs);
   }
 }
 
@@ -1029,13 +1101,19 @@ __global__ __launch_bounds__(256) void energy_kernel(const GroupView<real>* __re
 // ---------------------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------------------
-template <typename real>
-static const void* dp5_fn(bool fixed, int bs) {
+template <typename real, bool kL>
+static const void* dp5_fn_l(bool fixed, int bs) {
   if (bs == 512)
-    return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 512>)
-                 : reinterpret_cast<const void*>(&dp5_kernel<real, false, 512>);
-  return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 256>)
-               : reinterpret_cast<const void*>(&dp5_kernel<real, false, 256>);
+    return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 512, kL>)
+                 : reinterpret_cast<const void*>(&dp5_kernel<real, false, 512, kL>);
+  return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 256, kL>)
+               : reinterpret_cast<const void*>(&dp5_kernel<real, false, 256, kL>);
+}
+
+// kernel variant of a plan: the CSR view lives in LDS when the plan stages it
+template <typename real>
+static const void* dp5_fn(bool fixed, int bs, const LdsPlan& L) {
+  return L.csr_cap > 0 ? dp5_fn_l<real, true>(fixed, bs) : dp5_fn_l<real, false>(fixed, bs);
 }
 
 template <typename real>
@@ -1047,7 +1125,7 @@ hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int g
   const size_t shm = lds_plan_bytes<real>(L);
   LdsPlan Lc = L;
   void* args[] = {(void*)&d_groups, (void*)&P, (void*)&RB, (void*)&Lc};
-  const void* fn = dp5_fn<real>(fixed, bs);
+  const void* fn = dp5_fn<real>(fixed, bs, L);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(bs), args, shm, stream);
@@ -1058,7 +1136,7 @@ hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int g
 template <typename real>
 hipError_t max_coresident(const LdsPlan& L, bool fixed, int bs, int* per_cu, int* cus) {
   const size_t shm = lds_plan_bytes<real>(L);
-  const void* fn = dp5_fn<real>(fixed, bs);
+  const void* fn = dp5_fn<real>(fixed, bs, L);
   *per_cu = 0;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) {
