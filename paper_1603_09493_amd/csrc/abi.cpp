@@ -29,7 +29,7 @@ size_t dp5_lds_bytes(const LdsPlan&);
 template <typename real>
 hipError_t launch_dp5(const GroupView<real>*, const RunParams&, int, int, const LdsPlan&, bool, bool, hipStream_t, int);
 template <typename real>
-hipError_t max_coresident(const LdsPlan&, bool, int, int*, int*);
+hipError_t max_coresident(const LdsPlan&, bool, int, bool, int*, int*);
 template <typename real>
 hipError_t launch_energy(const GroupView<real>*, const int2*, int, const RunParams&, double*, int, hipStream_t);
 
@@ -482,10 +482,16 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   RB = std::min(RB, Rmax);
   if ((size_t)RB * ldS_max * sizeof(real) > 120 * 1024)
     return fail(c, BPM_EINVAL, "bpm_run: island too large for the LDS staging of the demag product");
-  LdsPlan L{Rmax, (sym ? 2 : 1) * RB * ldS_max, 0, 0, 0, ldS_max};
+  // dipole pair geometry of coupled instances staged in LDS for groups of up to 16 instances
+  bool any_coupled = false;
+  for (const auto& I : c->insts) any_coupled = any_coupled || I.coupled;
+  const int dip = (any_coupled && Rmax <= 16) ? Rmax : 0;
+  // rows longer than one round of the demag product keep per-wave round sums after the staged b
+  const int part = ldS_max > 12 * 64 * (int)(16 / sizeof(real)) ? (bs / 64) * 4 * 16 : 0;
+  LdsPlan L{Rmax, (sym ? 2 : 1) * RB * ldS_max + part, 0, 0, 0, ldS_max, dip};
   int per_cu = 0, cus = 0;
   {
-    hipError_t e = max_coresident<real>(L, fixed, bs, &per_cu, &cus);
+    hipError_t e = max_coresident<real>(L, fixed, bs, true, &per_cu, &cus);
     if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
     if (per_cu <= 0) return fail(c, BPM_EINVAL, "bpm_run: the stepping kernel does not fit a compute unit with this island size");
   }
@@ -530,12 +536,12 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     auto fits = [&](const LdsPlan& T) {
       if (dp5_lds_bytes<real>(T) > 160 * 1024) return false;
       int pc = 0, cu = 0;
-      return max_coresident<real>(T, fixed, bs, &pc, &cu) == hipSuccess && pc * cu >= grid;
+      return max_coresident<real>(T, fixed, bs, true, &pc, &cu) == hipSuccess && pc * cu >= grid;
     };
     bool found = false;
     if (!(o->flags & BPM_FLAG_STREAM_S) && !sym) {
       for (int rb = std::min(Rmax, 16); rb >= 1 && !found; --rb) {
-        LdsPlan T{Rmax, rb * ldS_max, nnz_max + 64, own_max, own_max, ldS_max};
+        LdsPlan T{Rmax, rb * ldS_max + part, nnz_max + 64, own_max, own_max, ldS_max, dip};
         if (fits(T)) { L = T; RB = rb; found = true; }
       }
     }

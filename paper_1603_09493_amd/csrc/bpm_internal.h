@@ -150,6 +150,7 @@ struct LdsPlan {
   int32_t own_cap;    // owned nodes (node data staged beside the CSR rows)
   int32_t s_rows;     // rows of S kept in LDS (0: S streamed from global memory)
   int32_t ldS;        // largest row stride of S in the launch
+  int32_t dip_slots;  // instances of the dipole pair-geometry table (0: computed on the fly)
 };
 
 std::string hip_err_string(hipError_t e);

@@ -72,6 +72,30 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum over a wave by DPP (pair and quad swaps, half-row and row mirrors, then the row broadcasts
+// 15 and 31); the total lands in lane 63.  Every lane of the wave must be active.
+template <int CTRL, int RM>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, RM, 0xF, false));
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, RM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RM, 0xF, false);
+  return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum_to63(T v) {
+  v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_add<0x140, 0xF>(v);   // row_mirror
+  v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Sum over a workgroup of BS threads; the result is valid in every thread.  `red` holds BS/64
 // doubles.
 template <int BS>
@@ -92,10 +116,8 @@ __device__ __forceinline__ float vcomp(const float4& v, int q) {
 }
 __device__ __forceinline__ double vcomp(const double2& v, int q) { return q == 0 ? v.x : v.y; }
 
-// Demag product shape: instances handled at once, 16-byte loads per lane per row in flight, rows
-// per wave processed together (each staged right-hand-side vector read from LDS serves RW rows).
-template <typename real> struct PhaseBShape { static constexpr int RMAX = 16, U = 8, RW = 2; };
-template <> struct PhaseBShape<double> { static constexpr int RMAX = 16, U = 4, RW = 2; };
+// instances handled at once by the symmetric demag product
+template <typename real> struct PhaseBShape { static constexpr int RMAX = 16; };
 
 struct GroupSync {
   unsigned long long* ctr;
@@ -103,21 +125,56 @@ struct GroupSync {
   int G;
 };
 
-// Barrier over the G workgroups of a mesh group.  Writes before the barrier are released at
-// agent scope by workgroup thread 0; the wait polls with relaxed agent-scope loads (no cache
-// invalidation per poll) and ends with one acquire fence, so every workgroup sees the writes.
+// Values exchanged between the workgroups of a mesh group within a launch (stage inputs, charges,
+// potentials) in a cooperative launch (kX) are written through to the agent coherence point and
+// read from it (agent-scope relaxed atomics: sc1 stores and loads), so that the group barrier
+// needs neither an L2 writeback nor an L2 invalidate; read-only data (S, the CSR arrays) and the
+// data each thread keeps for itself (m, the stage slopes, the exchange sums) stay cached.
+template <bool kX, typename T>
+__device__ __forceinline__ T xld(const GLB T* p) {
+  if constexpr (kX) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool kX, typename T>
+__device__ __forceinline__ void xst(GLB T* p, T v) {
+  if constexpr (kX) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+// the step-control accumulators are updated with device atomics and always read coherently
+__device__ __forceinline__ double acc_ld(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void acc_st(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier over the G workgroups of a mesh group.
+//  kX: every wave first waits until its own stores and atomics have completed at the coherence
+//      point (vmcnt(0); on gfx9 stores count there), then thread 0 arrives on the counter and
+//      polls it with relaxed agent-scope loads; the exchanged data are read with coherent loads
+//      afterwards, so no cache maintenance is needed.
+//  otherwise: thread 0 releases the workgroup's writes at agent scope (L2 writeback), polls, and
+//      acquires (L2 invalidate).
+template <bool kX>
 __device__ __forceinline__ void group_sync(GroupSync& s) {
-  __syncthreads();
   if (s.G > 1) {
+    if constexpr (kX) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt/lgkmcnt unconstrained
+    __syncthreads();
     s.target += (unsigned long long)s.G;
     if (threadIdx.x == 0) {
-      __hip_atomic_fetch_add(s.ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      while (__hip_atomic_load(s.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < s.target)
-        __builtin_amdgcn_s_sleep(1);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if constexpr (kX) {
+        __hip_atomic_fetch_add(s.ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (__hip_atomic_load(s.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < s.target)
+          __builtin_amdgcn_s_sleep(1);
+      } else {
+        __hip_atomic_fetch_add(s.ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        while (__hip_atomic_load(s.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < s.target)
+          __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 __device__ __forceinline__ double rise_of(const InstConst& c, double t) {
@@ -195,22 +252,32 @@ __host__ __device__ inline size_t csr_stage_bytes(int cap, int ocap) {
 static_assert(sizeof(InstConst) % 16 == 0, "instance constants are copied to LDS in 16-byte words");
 __host__ __device__ inline size_t ic_stage_bytes(int slots) { return (size_t)slots * sizeof(InstConst); }
 
+// pair geometry of dipole-coupled instances: unit vector from I to J and mu0 / (4 pi r^3)
+__host__ __device__ inline size_t dip_stage_bytes(int slots) { return (size_t)slots * slots * 4 * sizeof(double); }
+
 template <typename real>
 __host__ __device__ inline size_t lds_plan_bytes(const LdsPlan& L) {
-  return ic_stage_bytes(L.ic_slots) + ((size_t)L.bl_elems * sizeof(real) + 15) / 16 * 16 +
+  return ic_stage_bytes(L.ic_slots) + dip_stage_bytes(L.dip_slots) + ((size_t)L.bl_elems * sizeof(real) + 15) / 16 * 16 +
          csr_stage_bytes<real>(L.csr_cap, L.own_cap) + (size_t)L.s_rows * L.ldS * sizeof(real);
 }
 
 // copy `cnt` 16-byte words from global memory to LDS, UN loads of a thread in flight before its
-// stores
-template <int BS, int UN>
+// stores; kX: the source is exchanged data, read coherently as 8-byte halves
+template <int BS, int UN, bool kX>
 __device__ __forceinline__ void copy16(uint4* __restrict__ dst, const GLB uint4* __restrict__ src, int cnt) {
   for (int base = threadIdx.x; base < cnt; base += BS * UN) {
     uint4 v[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
       const int q = base + u * BS;
-      v[u] = src[q < cnt ? q : cnt - 1];   // in bounds on every lane; stored only where q < cnt
+      const int qq = q < cnt ? q : cnt - 1;   // in bounds on every lane; stored only where q < cnt
+      if constexpr (kX) {
+        const GLB unsigned long long* h = reinterpret_cast<const GLB unsigned long long*>(src + qq);
+        const unsigned long long lo = xld<true>(h), hi = xld<true>(h + 1);
+        v[u] = make_uint4((unsigned)lo, (unsigned)(lo >> 32), (unsigned)hi, (unsigned)(hi >> 32));
+      } else {
+        v[u] = src[qq];
+      }
     }
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
@@ -223,7 +290,7 @@ __device__ __forceinline__ void copy16(uint4* __restrict__ dst, const GLB uint4*
 // ---------------------------------------------------------------------------------------------
 // phase A: yex = K y, b = D (Ms y), dipole moments
 // ---------------------------------------------------------------------------------------------
-template <typename real, int BS, bool kL>
+template <typename real, int BS, bool kL, bool kX>
 __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
                                         int i0, int i1, const real* ysrc_, int ev, const Csr<real, kL>& cs) {
   const int n = g.n, nown = i1 - i0, ldS = g.ldS;
@@ -242,7 +309,7 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
     const GLB real* y = ysrc + (size_t)r * 3 * n;
     real ex0 = 0, ex1 = 0, ex2 = 0, bb = 0;
     const int qa = cs.rp[k], qb = cs.rp[k + 1];
-    const real own0 = y[i], own1 = y[n + i], own2 = y[2 * n + i];
+    const real own0 = xld<kX>(y + i), own1 = xld<kX>(y + n + i), own2 = xld<kX>(y + 2 * n + i);
     constexpr int kGather = Gather<real>::W;
     for (int q0 = qa; q0 < qb; q0 += kGather) {
       // all gathers of the row in flight at once (masked entries read the node itself)
@@ -253,7 +320,7 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
 #pragma unroll
       for (int u = 0; u < kGather; ++u) {
         const int j = cj[u] & 0xFFFF;
-        yx[u] = y[j]; yy[u] = y[n + j]; yz[u] = y[2 * n + j];
+        yx[u] = xld<kX>(y + j); yy[u] = xld<kX>(y + n + j); yz[u] = xld<kX>(y + 2 * n + j);
       }
 #pragma unroll
       for (int u = 0; u < kGather; ++u) {
@@ -272,7 +339,7 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
     yex[i] = ex0;
     yex[n + i] = ex1;
     yex[2 * n + i] = ex2;
-    bg[(size_t)r * ldS + i] = bb;
+    xst<kX>(bg + (size_t)r * ldS + i, bb);
     if (c.coupled[r]) {
       const double w = (double)(cs.lay[k] ? Ms1 : Ms0) * (double)cs.V[k];
       atomicAdd(&c.accL[r][0], w * (double)own0);
@@ -293,27 +360,90 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
 // ---------------------------------------------------------------------------------------------
 // phase B: u = S b for the owned rows; b of up to RB instances staged in LDS.  kSL: the owned
 // rows of S are resident in LDS (SL, row k = node i0 + k), else they stream from global memory.
-// Each wave takes RW rows at a time; per row the sum over columns is per lane, then over the wave
-// (the same order for either source of S).
+// A wave takes RWb rows at a time and loads UM 16-byte words of each per lane and round (a round
+// covers UM * 64 * VEC columns, the whole row up to 3072 FP32 columns), so about 12 loads per
+// lane are in flight;
+// then, instance by instance, it reads the staged b words of the same columns, forms the lane
+// partial dot products (over the lane's columns, in column order) and sums them over the wave.
+// Rows longer than one round add the round sums in a per-wave LDS slot.  The order of every sum
+// is the same for either source of S.
 // ---------------------------------------------------------------------------------------------
-template <typename real, int BS, bool kSL>
-__device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* bL,
-                                        const real* SL, int RB) {
+template <typename real, int BS, bool kSL, bool kX, int UM, int RWb>
+__device__ __forceinline__ void demag_rows(const GroupView<real>& g, int i0, int nr, const real* bL, const real* SL,
+                                           real* part, int rb, int rn) {
   const int ldS = g.ldS;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   constexpr int nw = BS / 64;
   constexpr int VEC = 16 / sizeof(real);
-  constexpr int U = PhaseBShape<real>::U;         // 16-byte loads per lane and row in flight
-  constexpr int RMAX = PhaseBShape<real>::RMAX;
-  constexpr int RW = PhaseBShape<real>::RW;
-  constexpr int STEP = 64 * VEC;                  // elements one wave covers per load
+  constexpr int STEP = 64 * VEC;
   using vec_t = typename std::conditional<sizeof(real) == 4, float4, double2>::type;
   using sptr = typename std::conditional<kSL, const real*, const GLB real*>::type;
   using vptr = typename std::conditional<kSL, const vec_t*, const GLB vec_t*>::type;
   const sptr Sbase = kSL ? (sptr)SL : (sptr)(glb(g.S) + (size_t)i0 * ldS);
   GLB real* __restrict__ ug = glb(g.u);
+  real* pw = part + wid * 4 * 16;          // this wave's round sums [RWb <= 4][16]
+  const bool multi = ldS > UM * STEP;
+  for (int k0 = wid * RWb; k0 < nr; k0 += nw * RWb) {
+    sptr Srow[RWb];
+#pragma unroll
+    for (int w = 0; w < RWb; ++w) Srow[w] = Sbase + (size_t)min(k0 + w, nr - 1) * ldS;
+    for (int base = 0; base < ldS; base += UM * STEP) {      // wave-uniform rounds
+      vec_t sv[RWb][UM];
+#pragma unroll
+      for (int u = 0; u < UM; ++u) {
+        const int l = base + u * STEP + lane * VEC;
+#pragma unroll
+        for (int w = 0; w < RWb; ++w) {
+          if (l < ldS) sv[w][u] = *reinterpret_cast<vptr>(Srow[w] + l);
+          else sv[w][u] = vec_t{};
+        }
+      }
+#pragma unroll 1
+      for (int r = 0; r < rn; ++r) {
+        vec_t bv[UM];
+#pragma unroll
+        for (int u = 0; u < UM; ++u) {
+          const int l = min(base + u * STEP + lane * VEC, ldS - VEC);   // in bounds; S is zero beyond ldS
+          bv[u] = *reinterpret_cast<const vec_t*>(bL + r * ldS + l);
+        }
+        real a[RWb];
+#pragma unroll
+        for (int w = 0; w < RWb; ++w) {
+          a[w] = 0;
+#pragma unroll
+          for (int u = 0; u < UM; ++u)
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) a[w] += vcomp(sv[w][u], q) * vcomp(bv[u], q);
+        }
+#pragma unroll
+        for (int w = 0; w < RWb; ++w) {
+          const real t = wave_sum_to63(a[w]);
+          if (lane == 63) {
+            if (!multi) {
+              if (k0 + w < nr) xst<kX>(ug + (size_t)(rb + r) * ldS + i0 + k0 + w, t);
+            } else {
+              pw[w * 16 + r] = base == 0 ? t : pw[w * 16 + r] + t;
+            }
+          }
+        }
+      }
+    }
+    if (multi && lane == 63)
+      for (int w = 0; w < RWb; ++w)
+        for (int r = 0; r < rn; ++r)
+          if (k0 + w < nr) xst<kX>(ug + (size_t)(rb + r) * ldS + i0 + k0 + w, pw[w * 16 + r]);
+  }
+}
+
+template <typename real, int BS, bool kSL, bool kX>
+__device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0, int i1, real* bL,
+                                        const real* SL, real* part, int RB) {
+  const int ldS = g.ldS;
+  constexpr int VEC = 16 / sizeof(real);
+  constexpr int STEP = 64 * VEC;
   const int nr = i1 - i0;
-  RB = min(RB, RMAX);
+  const int U = (ldS + STEP - 1) / STEP;   // 16-byte words per lane and row
+  RB = min(RB, 16);
   for (int rb = 0; rb < g.R; rb += RB) {
     const int rn = min(RB, g.R - rb);
     bool any = false;
@@ -321,56 +451,12 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
     if (!any) continue;
     __syncthreads();
     // b rows are ldS long (zero padded), so the staging is one contiguous 16-byte copy
-    copy16<BS, 16>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
-                   rn * ldS / VEC);
+    copy16<BS, 16, kX>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
+                       rn * ldS / VEC);
     __syncthreads();
-    for (int k0 = wid * RW; k0 < nr; k0 += nw * RW) {
-      sptr Srow[RW];
-#pragma unroll
-      for (int w = 0; w < RW; ++w) Srow[w] = Sbase + (size_t)min(k0 + w, nr - 1) * ldS;
-      real acc[RW][RMAX];
-#pragma unroll
-      for (int w = 0; w < RW; ++w)
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) acc[w][r] = 0;
-      for (int l0 = lane * VEC; l0 < ldS; l0 += STEP * U) {
-        vec_t sv[RW][U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int l = l0 + u * STEP;
-#pragma unroll
-          for (int w = 0; w < RW; ++w) {
-            if (l < ldS) sv[w][u] = *reinterpret_cast<vptr>(Srow[w] + l);
-            else sv[w][u] = vec_t{};
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int l = l0 + u * STEP;
-          if (l >= ldS) break;
-#pragma unroll
-          for (int r = 0; r < RMAX; ++r) {
-            if (r < rn) {
-              const vec_t bv = *reinterpret_cast<const vec_t*>(bL + r * ldS + l);
-#pragma unroll
-              for (int w = 0; w < RW; ++w)
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) acc[w][r] += vcomp(sv[w][u], q) * vcomp(bv, q);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int w = 0; w < RW; ++w) {
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-          if (r < rn) {
-            const real v = wave_sum(acc[w][r]);
-            if (lane == 0 && k0 + w < nr) ug[(size_t)(rb + r) * ldS + i0 + k0 + w] = v;
-          }
-        }
-      }
-    }
+    if (U <= 3) demag_rows<real, BS, kSL, kX, 3, 4>(g, i0, nr, bL, SL, part, rb, rn);
+    else if (U <= 6) demag_rows<real, BS, kSL, kX, 6, 2>(g, i0, nr, bL, SL, part, rb, rn);
+    else demag_rows<real, BS, kSL, kX, 12, 1>(g, i0, nr, bL, SL, part, rb, rn);   // several rounds beyond 12
   }
 }
 
@@ -398,8 +484,8 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
     for (int r = rb; r < rb + rn; ++r) any = any || c.active[c.isys[r]];
     if (!any) continue;
     __syncthreads();
-    copy16<BS, 16>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
-                   rn * ldS / VEC);
+    copy16<BS, 16, false>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
+                          rn * ldS / VEC);
     for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) uL[idx] = (real)0;
     __syncthreads();
     for (int k = wid; k < n; k += nw) {
@@ -462,7 +548,7 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
 // magnetisation, exchange sums, potentials of the CSR row, m and the earlier stages) is issued
 // before the arithmetic that consumes it.  s is uniform over the workgroup, so the loads of the
 // stages below s are predicated by scalar branches and stay in flight together.
-template <typename real, bool kL>
+template <typename real, bool kL, bool kX>
 __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst& ic,
                                        int s, int r, int k, int i0, int sl, const GLB real* __restrict__ ysrc,
                                        GLB real* __restrict__ ydst, const Csr<real, kL>& cs) {
@@ -482,9 +568,9 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
   const int p = cs.pt[k];
   const int pp = p >= 0 ? p : i;
   // loads
-  const real mx = y[i], my = y[n + i], mz = y[2 * n + i];
+  const real mx = xld<kX>(y + i), my = xld<kX>(y + n + i), mz = xld<kX>(y + 2 * n + i);
   const real ex0 = yex[i], ex1 = yex[n + i], ex2 = yex[2 * n + i];
-  const real px = y[pp], py = y[n + pp], pz = y[2 * n + pp];
+  const real px = xld<kX>(y + pp), py = xld<kX>(y + n + pp), pz = xld<kX>(y + 2 * n + pp);
   real mm[3], kl[6][3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) mm[d] = m[d * n + i];
@@ -499,7 +585,7 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
   for (int q0 = qa; q0 < qb; q0 += kGather) {
     real uq[kGather];
 #pragma unroll
-    for (int w = 0; w < kGather; ++w) uq[w] = u[q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i];
+    for (int w = 0; w < kGather; ++w) uq[w] = xld<kX>(u + (q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i));
 #pragma unroll
     for (int w = 0; w < kGather; ++w) {
       const int q = q0 + w;
@@ -549,7 +635,7 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
     }
     const real ha = (real)(h * kA[s + 1][s]);
     v[0] += ha * kx; v[1] += ha * ky; v[2] += ha * kz;
-    yn[i] = v[0]; yn[n + i] = v[1]; yn[2 * n + i] = v[2];
+    xst<kX>(yn + i, v[0]); xst<kX>(yn + n + i, v[1]); xst<kX>(yn + 2 * n + i, v[2]);
     if (s == 5) {
       // observables of the normalised candidate
       const double nr = sqrt((double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2]);
@@ -586,37 +672,55 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
   }
 }
 
-template <typename real, bool kFixed, int BS, bool kL>
+template <typename real, bool kFixed, int BS, bool kL, bool kX>
 __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
-                                        int i0, int i1, int s, const real* ysrc_, real* ydst_, int it, int ev,
-                                        const Csr<real, kL>& cs) {
+                                        const double* dipL, int i0, int i1, int s, const real* ysrc_, real* ydst_,
+                                        int it, int ev, const Csr<real, kL>& cs) {
   const int nown = i1 - i0;
   const GLB real* ysrc = glb(ysrc_);
   GLB real* ydst = glb(ydst_);
   // dipole fields of coupled instances from the moments of this stage
   if (c.any_coupled) {
     for (int q = threadIdx.x; q < g.R * 3; q += BS)
-      c.mom[q / 3][q % 3] = P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + ev % 3) * 3 + q % 3];
+      c.mom[q / 3][q % 3] = acc_ld(&P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + ev % 3) * 3 + q % 3]);
     __syncthreads();
-    for (int J = threadIdx.x; J < g.R; J += BS) {
-      double B0 = 0.0, B1 = 0.0, B2 = 0.0;
-      if (c.coupled[J]) {
-        const InstConst& cj = icL[J];
-        for (int I = 0; I < g.R; ++I) {
-          if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
-          const InstConst& ci = icL[I];
-          const double* mu = c.mom[I];
-          const double d0 = cj.off[0] - ci.off[0], d1 = cj.off[1] - ci.off[1], d2 = cj.off[2] - ci.off[2];
-          const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-          const double e0 = d0 / rr, e1 = d1 / rr, e2 = d2 / rr;
-          const double mr = mu[0] * e0 + mu[1] * e1 + mu[2] * e2;
-          const double f = kMu0 / (4.0 * kPi * rr * rr * rr);
-          B0 += f * (3.0 * mr * e0 - mu[0]);
-          B1 += f * (3.0 * mr * e1 - mu[1]);
-          B2 += f * (3.0 * mr * e2 - mu[2]);
+    if (dipL) {
+      // one (instance, component) per thread from the pair geometry staged at launch start
+      for (int q = threadIdx.x; q < g.R * 3; q += BS) {
+        const int J = q / 3, d = q - 3 * J;
+        double B = 0.0;
+        if (c.coupled[J]) {
+          for (int I = 0; I < g.R; ++I) {
+            if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
+            const double* gJI = dipL + ((size_t)J * g.R + I) * 4;
+            const double* mu = c.mom[I];
+            const double mr = mu[0] * gJI[0] + mu[1] * gJI[1] + mu[2] * gJI[2];
+            B += gJI[3] * (3.0 * mr * gJI[d] - mu[d]);
+          }
         }
+        c.Bdip[J][d] = B;
       }
-      c.Bdip[J][0] = B0; c.Bdip[J][1] = B1; c.Bdip[J][2] = B2;
+    } else {
+      for (int J = threadIdx.x; J < g.R; J += BS) {
+        double B0 = 0.0, B1 = 0.0, B2 = 0.0;
+        if (c.coupled[J]) {
+          const InstConst& cj = icL[J];
+          for (int I = 0; I < g.R; ++I) {
+            if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
+            const InstConst& ci = icL[I];
+            const double* mu = c.mom[I];
+            const double d0 = cj.off[0] - ci.off[0], d1 = cj.off[1] - ci.off[1], d2 = cj.off[2] - ci.off[2];
+            const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const double e0 = d0 / rr, e1 = d1 / rr, e2 = d2 / rr;
+            const double mr = mu[0] * e0 + mu[1] * e1 + mu[2] * e2;
+            const double f = kMu0 / (4.0 * kPi * rr * rr * rr);
+            B0 += f * (3.0 * mr * e0 - mu[0]);
+            B1 += f * (3.0 * mr * e1 - mu[1]);
+            B2 += f * (3.0 * mr * e2 - mu[2]);
+          }
+        }
+        c.Bdip[J][0] = B0; c.Bdip[J][1] = B1; c.Bdip[J][2] = B2;
+      }
     }
   }
   if (s >= 5) {
@@ -628,7 +732,7 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
     const int r = it2 / nown, k = it2 - r * nown;
     const int sl = c.isys[r];
     if (!c.active[sl]) continue;
-    pair_C<real, kL>(g, P, c, icL[r], s, r, k, i0, sl, ysrc, ydst, cs);
+    pair_C<real, kL, kX>(g, P, c, icL[r], s, r, k, i0, sl, ysrc, ydst, cs);
   }
   if (s >= 5) {
     __syncthreads();
@@ -648,18 +752,19 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
   }
 }
 
-template <typename real, bool kFixed, int BS, bool kL>
+template <typename real, bool kFixed, int BS, bool kL, bool kX>
 __device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
-                                           GroupSync& gs, int i0, int i1, int s, const real* ysrc, real* ydst,
-                                           int it, int ev, real* bL, const real* SL, int RB, const Csr<real, kL>& cs) {
-  phase_A<real, BS, kL>(g, P, c, icL, i0, i1, ysrc, ev, cs);
-  group_sync(gs);
-  if (SL) phase_B<real, BS, true>(g, c, i0, i1, bL, SL, RB);
-  else if (g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real, BS>(g, c, bL, RB);
-  else phase_B<real, BS, false>(g, c, i0, i1, bL, nullptr, RB);
-  group_sync(gs);
-  phase_C<real, kFixed, BS, kL>(g, P, c, icL, i0, i1, s, ysrc, ydst, it, ev, cs);
-  group_sync(gs);
+                                           const double* dipL, GroupSync& gs, int i0, int i1, int s, const real* ysrc,
+                                           real* ydst, int it, int ev, real* bL, const real* SL, real* part, int RB,
+                                           const Csr<real, kL>& cs) {
+  phase_A<real, BS, kL, kX>(g, P, c, icL, i0, i1, ysrc, ev, cs);
+  group_sync<kX>(gs);
+  if (SL) phase_B<real, BS, true, kX>(g, c, i0, i1, bL, SL, part, RB);
+  else if (!kX && g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real, BS>(g, c, bL, RB);
+  else phase_B<real, BS, false, kX>(g, c, i0, i1, bL, nullptr, part, RB);
+  group_sync<kX>(gs);
+  phase_C<real, kFixed, BS, kL, kX>(g, P, c, icL, dipL, i0, i1, s, ysrc, ydst, it, ev, cs);
+  group_sync<kX>(gs);
 }
 
 // trajectory sample of instance r (called by one thread of the group's first workgroup)
@@ -705,9 +810,10 @@ __device__ __forceinline__ void plan_attempt(const RunParams& P, Ctl& c, int nsy
   }
 }
 
-template <typename real, bool kFixed, int BS, bool kL>
+template <typename real, bool kFixed, int BS, bool kL, bool kX>
 __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
-                                         int w, real* bL, const real* SL, int RB, const Csr<real, kL>& cs) {
+                                         double* dipL, int w, real* bL, const real* SL, real* part, int RB,
+                                         const Csr<real, kL>& cs) {
   const int n = g.n;
   const int i0 = (int)((long long)n * w / g.G), i1 = (int)((long long)n * (w + 1) / g.G);
   const int nown = i1 - i0;
@@ -739,6 +845,21 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
     }
   }
   __syncthreads();
+  if (dipL) {
+    // pair geometry of the coupled instances, the same expressions as the on-the-fly path
+    for (int q = threadIdx.x; q < g.R * g.R; q += BS) {
+      const int J = q / g.R, I = q - J * g.R;
+      double* gJI = dipL + (size_t)q * 4;
+      gJI[0] = gJI[1] = gJI[2] = gJI[3] = 0.0;
+      if (I == J) continue;
+      const double d0 = icL[J].off[0] - icL[I].off[0], d1 = icL[J].off[1] - icL[I].off[1];
+      const double d2 = icL[J].off[2] - icL[I].off[2];
+      const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      gJI[0] = d0 / rr; gJI[1] = d1 / rr; gJI[2] = d2 / rr;
+      gJI[3] = kMu0 / (4.0 * kPi * rr * rr * rr);
+    }
+    __syncthreads();
+  }
 
   // ---- prologue: stage input = m0, observables of m0, first right-hand side
   real* ys0 = g.ys;
@@ -754,7 +875,7 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       v[d] = mg[(size_t)r * st3 + d * n + i];
-      glb(ys0)[(size_t)r * st3 + d * n + i] = v[d];
+      xst<kX>(glb(ys0) + (size_t)r * st3 + d * n + i, v[d]);
     }
     atomicAdd(&c.accL[r][L ? 1 : 0], Vd * (double)v[2]);
     atomicAdd(&c.accL[r][2], Ms * Vd * (double)v[0]);
@@ -764,7 +885,7 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
   __syncthreads();
   for (int q = threadIdx.x; q < g.R * 5; q += BS)
     atomicAdd(&P.obs_acc[((size_t)(g.inst0 + q / 5) * 3 + 2) * 6 + q % 5], c.accL[q / 5][q % 5]);
-  group_sync(gs);
+  group_sync<kX>(gs);
   // One call site of the field evaluation (its code is large): the evaluation of stage 0 of the
   // prologue is the first pass of the loop, then stages 1..6 of every attempt.
   int ev = 0, it = 0, s = 0;
@@ -781,22 +902,24 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
       // clear the accumulators used two attempts ago (every workgroup has read them)
       if (lead) {
         for (int r = threadIdx.x; r < g.R; r += BS)
-          for (int d = 0; d < 6; ++d) P.obs_acc[((size_t)(g.inst0 + r) * 3 + (it + 2) % 3) * 6 + d] = 0.0;
-        for (int sl = threadIdx.x; sl < g.nsys; sl += BS) P.err_acc[(size_t)(g.sys0 + sl) * 3 + (it + 2) % 3] = 0.0;
+          for (int d = 0; d < 6; ++d) acc_st(&P.obs_acc[((size_t)(g.inst0 + r) * 3 + (it + 2) % 3) * 6 + d], 0.0);
+        for (int sl = threadIdx.x; sl < g.nsys; sl += BS) acc_st(&P.err_acc[(size_t)(g.sys0 + sl) * 3 + (it + 2) % 3], 0.0);
       }
     }
     if (s >= 1 && lead && c.any_coupled)
       for (int r = threadIdx.x; r < g.R; r += BS)
-        for (int d = 0; d < 3; ++d) P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 2) % 3) * 3 + d] = 0.0;
+        for (int d = 0; d < 3; ++d) acc_st(&P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 2) % 3) * 3 + d], 0.0);
     {
       const real* src = (s & 1) ? ys1 : ys0;
       real* dst = (s & 1) ? ys0 : ys1;
-      field_eval<real, kFixed, BS, kL>(g, P, c, icL, gs, i0, i1, s, src, dst, it, ev++, bL, SL, RB, cs);
+      field_eval<real, kFixed, BS, kL, kX>(g, P, c, icL, dipL, gs, i0, i1, s, src, dst, it, ev++, bL, SL, part, RB, cs);
     }
     if (s == 0) {
       // initial observables, crossing state, first trajectory sample
       for (int r = threadIdx.x; r < g.R; r += BS) {
-        const double* ob = &P.obs_acc[((size_t)(g.inst0 + r) * 3 + 2) * 6];
+        double ob[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) ob[d] = acc_ld(&P.obs_acc[((size_t)(g.inst0 + r) * 3 + 2) * 6 + d]);
         const double vh = g.Vhard > 0 ? ob[1] / g.Vhard : 0.0;
         c.prev_t[r] = 0.0; c.prev_v[r] = vh;
         c.mzs[r] = g.Vsoft > 0 ? ob[0] / g.Vsoft : 0.0; c.mzh[r] = vh;
@@ -815,9 +938,9 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         const GLB real* k0 = kg + (size_t)r * 7 * st3;
         GLB real* yn = glb(ys1) + (size_t)r * st3;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) yn[d * n + i] = m[d * n + i] + ha * k0[d * n + i];
+        for (int d = 0; d < 3; ++d) xst<kX>(yn + d * n + i, m[d * n + i] + ha * k0[d * n + i]);
       }
-      group_sync(gs);
+      group_sync<kX>(gs);
       s = 1;
       continue;
     }
@@ -830,7 +953,7 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
     for (int sl = threadIdx.x; sl < g.nsys; sl += BS) {
       c.accepted[sl] = 0;
       if (!c.active[sl]) continue;
-      const double acc = P.err_acc[(size_t)(g.sys0 + sl) * 3 + it % 3];
+      const double acc = acc_ld(&P.err_acc[(size_t)(g.sys0 + sl) * 3 + it % 3]);
       const double err = sqrt(acc / (3.0 * (double)n * (double)c.ninst[sl]));
       const double h = c.h[sl];
       c.err[sl] = err;
@@ -864,7 +987,9 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
     for (int r = threadIdx.x; r < g.R; r += BS) {
       const int sl = c.isys[r];
       if (!c.accepted[sl]) continue;
-      const double* ob = &P.obs_acc[((size_t)(g.inst0 + r) * 3 + it % 3) * 6];
+      double ob[6];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) ob[d] = acc_ld(&P.obs_acc[((size_t)(g.inst0 + r) * 3 + it % 3) * 6 + d]);
       const double vh = g.Vhard > 0 ? ob[1] / g.Vhard : 0.0;
       const double t = c.t[sl];
       c.mzs[r] = g.Vsoft > 0 ? ob[0] / g.Vsoft : 0.0; c.mzh[r] = vh;
@@ -882,8 +1007,7 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
       if (!c.accepted[sl]) continue;
       for (int r = 0; r < g.R; ++r) {
         if (c.isys[r] != sl) continue;
-        const double* ob = &P.obs_acc[((size_t)(g.inst0 + r) * 3 + it % 3) * 6];
-        const double dev = __longlong_as_double((long long)reinterpret_cast<const unsigned long long*>(ob)[5]);
+        const double dev = acc_ld(&P.obs_acc[((size_t)(g.inst0 + r) * 3 + it % 3) * 6 + 5]);
         if (dev > c.maxdev[sl]) c.maxdev[sl] = dev;
       }
     }
@@ -902,7 +1026,7 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
       if (acc) {
         const GLB real* y7 = glb(ys0) + (size_t)r * st3;
         const GLB real* k6 = k0 + 6 * st3;
-        const real a = y7[i], b = y7[n + i], d = y7[2 * n + i];
+        const real a = xld<kX>(y7 + i), b = xld<kX>(y7 + n + i), d = xld<kX>(y7 + 2 * n + i);
         kv[0] = k6[i]; kv[1] = k6[n + i]; kv[2] = k6[2 * n + i];
         const real inv = (real)1 / sqrt(a * a + b * b + d * d);
         mv[0] = a * inv; mv[1] = b * inv; mv[2] = d * inv;
@@ -916,10 +1040,10 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         const real ha = (real)(c.h[sl] * kA[1][0]);
         GLB real* yn = glb(ys1) + (size_t)r * st3;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) yn[d * n + i] = mv[d] + ha * kv[d];
+        for (int d = 0; d < 3; ++d) xst<kX>(yn + d * n + i, mv[d] + ha * kv[d]);
       }
     }
-    group_sync(gs);
+    group_sync<kX>(gs);
     ++it;
   }
   // results (every system of the group has finished)
@@ -938,7 +1062,7 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
 }
 
 
-template <typename real, bool kFixed, int BS, bool kL>
+template <typename real, bool kFixed, int BS, bool kL, bool kX>
 __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restrict__ groups,
                                                  RunParams P, int RB, LdsPlan LP) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -953,18 +1077,23 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
   unsigned char* lp = smem_raw;
   InstConst* icL = reinterpret_cast<InstConst*>(lp);
   lp += ic_stage_bytes(LP.ic_slots);
+  double* dipL = LP.dip_slots >= g.R ? reinterpret_cast<double*>(lp) : nullptr;
+  lp += dip_stage_bytes(LP.dip_slots);
   real* bL = reinterpret_cast<real*>(lp);
   lp += ((size_t)LP.bl_elems * sizeof(real) + 15) / 16 * 16;
+  // per-wave round sums of the demag product for rows longer than one round (the launch plan
+  // reserves them at the end of the right-hand-side area when such rows can occur)
+  real* part = LP.ldS > 12 * (64 * (int)(16 / sizeof(real))) ? bL + LP.bl_elems - (BS / 64) * 4 * 16 : bL;
   unsigned char* csr_lds = lp;
   lp += csr_stage_bytes<real>(LP.csr_cap, LP.own_cap);
   // S rows are resident only when this workgroup's rows fit the planned area
   real* SL = (LP.s_rows > 0 && nown <= LP.s_rows) ? reinterpret_cast<real*>(lp) : nullptr;
-  copy16<BS, 4>(reinterpret_cast<uint4*>(icL), reinterpret_cast<const GLB uint4*>(glb(P.inst + g.inst0)),
+  copy16<BS, 4, false>(reinterpret_cast<uint4*>(icL), reinterpret_cast<const GLB uint4*>(glb(P.inst + g.inst0)),
                 (int)(g.R * sizeof(InstConst) / 16));
   if (SL) {
     // the owned rows of S, once for the whole launch
     constexpr int VEC = 16 / sizeof(real);
-    copy16<BS, 8>(reinterpret_cast<uint4*>(SL), reinterpret_cast<const GLB uint4*>(glb(g.S) + (size_t)i0 * ldS),
+    copy16<BS, 8, false>(reinterpret_cast<uint4*>(SL), reinterpret_cast<const GLB uint4*>(glb(g.S) + (size_t)i0 * ldS),
                   nown * ldS / VEC);
   }
   if constexpr (kL) {
@@ -1004,13 +1133,13 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
     }
     const Csr<real, true> cs{rpL, colL, KL, DL, DTL, ptL, layL, VL, aL, xL, yL};
     __syncthreads();
-    dp5_body<real, kFixed, BS, true>(g, P, c, icL, w, bL, SL, RB, cs);
+    dp5_body<real, kFixed, BS, true, kX>(g, P, c, icL, dipL, w, bL, SL, part, RB, cs);
   } else {
     const Csr<real, false> cs{glb(g.rowptr) + i0, glb(g.colx), glb(g.K), glb(g.D), glb(g.DT),
                               glb(g.partner) + i0, glb(g.layer) + i0, glb(g.V) + i0, glb(g.aif) + i0,
                               glb(g.x) + i0, glb(g.y) + i0};
     __syncthreads();
-    dp5_body<real, kFixed, BS, false>(g, P, c, icL, w, bL, SL, RB, cs);
+    dp5_body<real, kFixed, BS, false, kX>(g, P, c, icL, dipL, w, bL, SL, part, RB, cs);
   }
 }
 
@@ -1101,19 +1230,21 @@ __global__ __launch_bounds__(256) void energy_kernel(const GroupView<real>* __re
 // ---------------------------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------------------------
-template <typename real, bool kL>
+template <typename real, bool kL, bool kX>
 static const void* dp5_fn_l(bool fixed, int bs) {
   if (bs == 512)
-    return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 512, kL>)
-                 : reinterpret_cast<const void*>(&dp5_kernel<real, false, 512, kL>);
-  return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 256, kL>)
-               : reinterpret_cast<const void*>(&dp5_kernel<real, false, 256, kL>);
+    return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 512, kL, kX>)
+                 : reinterpret_cast<const void*>(&dp5_kernel<real, false, 512, kL, kX>);
+  return fixed ? reinterpret_cast<const void*>(&dp5_kernel<real, true, 256, kL, kX>)
+               : reinterpret_cast<const void*>(&dp5_kernel<real, false, 256, kL, kX>);
 }
 
-// kernel variant of a plan: the CSR view lives in LDS when the plan stages it
+// kernel variant of a launch: cooperative launches (groups spanning several workgroups) use the
+// coherent exchange protocol, with the CSR view in LDS when the plan stages it
 template <typename real>
-static const void* dp5_fn(bool fixed, int bs, const LdsPlan& L) {
-  return L.csr_cap > 0 ? dp5_fn_l<real, true>(fixed, bs) : dp5_fn_l<real, false>(fixed, bs);
+static const void* dp5_fn(bool fixed, int bs, const LdsPlan& L, bool coop) {
+  if (!coop) return dp5_fn_l<real, false, false>(fixed, bs);
+  return L.csr_cap > 0 ? dp5_fn_l<real, true, true>(fixed, bs) : dp5_fn_l<real, false, true>(fixed, bs);
 }
 
 template <typename real>
@@ -1125,7 +1256,7 @@ hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int g
   const size_t shm = lds_plan_bytes<real>(L);
   LdsPlan Lc = L;
   void* args[] = {(void*)&d_groups, (void*)&P, (void*)&RB, (void*)&Lc};
-  const void* fn = dp5_fn<real>(fixed, bs, L);
+  const void* fn = dp5_fn<real>(fixed, bs, L, cooperative);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(bs), args, shm, stream);
@@ -1134,9 +1265,9 @@ hipError_t launch_dp5(const GroupView<real>* d_groups, const RunParams& P, int g
 
 // resident workgroups per CU of the stepping kernel with this LDS plan (0 if it does not fit)
 template <typename real>
-hipError_t max_coresident(const LdsPlan& L, bool fixed, int bs, int* per_cu, int* cus) {
+hipError_t max_coresident(const LdsPlan& L, bool fixed, int bs, bool coop, int* per_cu, int* cus) {
   const size_t shm = lds_plan_bytes<real>(L);
-  const void* fn = dp5_fn<real>(fixed, bs, L);
+  const void* fn = dp5_fn<real>(fixed, bs, L, coop);
   *per_cu = 0;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) {
@@ -1167,8 +1298,8 @@ template size_t dp5_lds_bytes<float>(const LdsPlan&);
 template size_t dp5_lds_bytes<double>(const LdsPlan&);
 template hipError_t launch_dp5<float>(const GroupView<float>*, const RunParams&, int, int, const LdsPlan&, bool, bool, hipStream_t, int);
 template hipError_t launch_dp5<double>(const GroupView<double>*, const RunParams&, int, int, const LdsPlan&, bool, bool, hipStream_t, int);
-template hipError_t max_coresident<float>(const LdsPlan&, bool, int, int*, int*);
-template hipError_t max_coresident<double>(const LdsPlan&, bool, int, int*, int*);
+template hipError_t max_coresident<float>(const LdsPlan&, bool, int, bool, int*, int*);
+template hipError_t max_coresident<double>(const LdsPlan&, bool, int, bool, int*, int*);
 template hipError_t launch_energy<float>(const GroupView<float>*, const int2*, int, const RunParams&, double*, int, hipStream_t);
 template hipError_t launch_energy<double>(const GroupView<double>*, const int2*, int, const RunParams&, double*, int, hipStream_t);
 
