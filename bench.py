@@ -123,6 +123,40 @@ def batch_leg(n_islands=4096, t_end=1e-11, steps=1):
             "status_ok": int(sum(1 for r in res if r["status"] == 0))}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "dp5_kernel_patch_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1603_09493_amd", "csrc", "llg_kernels.hip")
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_per_eval():
+    """HBM bytes per field evaluation of the stepping kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE of one profiled launch, each scaled by what the counter
+    reads for a device copy of known size), or None when the summary is missing or was taken on a
+    different kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv["kernel_source_sha256"] != kernel_source_sha():
+            return None
+        evals = float(kv["evals_per_launch"])
+        fetch = float(kv["fetch_kib_per_launch"]) * 1024 * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_launch"]) * 1024 * float(kv["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) / evals
+
+
 def copy_calibration(mib=512, reps=3):
     """A plain device copy of known size (for scaling the profiler's byte counters)."""
     import torch
@@ -142,7 +176,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--t-end", type=float, default=1e-9)
     ap.add_argument("--precision", type=int, default=32)
-    ap.add_argument("--wg", type=int, default=0, help="workgroups per mesh group (0 = auto)")
+    ap.add_argument("--wg", type=int, default=0,
+                    help="workgroups per mesh group (0 = autotune; negative = that many 512-thread workgroups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 512 MiB device copy (profiling)")
@@ -167,7 +202,8 @@ def main():
     asm = ctx.mesh_get_assembly(mid)
     nnz = int(asm["rowptr"][-1])
     rtol = 1e-5 if args.precision == 32 else 1e-6
-    run_kw = dict(t_end=args.t_end, precision=args.precision, rtol=rtol, wg_per_group=args.wg)
+    run_kw = dict(t_end=args.t_end, precision=args.precision, rtol=rtol, wg_per_group=abs(args.wg),
+                  flags=bpm.FLAG_WG512 if args.wg < 0 else 0)
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -175,7 +211,8 @@ def main():
     log(f"patch: {len(ids)} islands x {mesh.n} nodes, setup {setup_s:.1f} s")
     tuned = None
     if args.wg == 0:
-        cands = [16, 32, 48, 64, 96, 128, 192, 256]
+        # workgroups per group; negative = 512-thread workgroups
+        cands = [32, 64, 96, 128, 192, 256, -48, -64, -96, -128, -192, -256]
         tuned, ms = ctx.autotune(cands, probe_attempts=80, t_end=args.t_end, precision=args.precision, rtol=rtol)
         log("autotune (us/attempt): " + ", ".join(f"{c}:{1e3*m:.0f}" for c, m in zip(cands, ms)) + f" -> {tuned}")
     for w in range(args.warmup):
@@ -205,6 +242,7 @@ def main():
     fl = roofline.eval_flops(mesh.n, nnz, len(ids)) * evals
     k_ms = kernel_ms[-1]
     achieved = by / (k_ms * 1e-3) / 1e9
+    tpe = traffic_per_eval()
     out = {
         "metric": METRIC,
         "value": value,
@@ -227,6 +265,7 @@ def main():
             "nnz": nnz,
             "simulated_ns": args.t_end * 1e9,
             "wg_per_group": ctx.last_run_info()["wg_per_group"],
+            "threads_per_wg": ctx.last_run_layout()["threads"],
             "autotuned_wg_per_group": tuned,
             "grid": ctx.last_run_info()["grid"],
             "attempts": attempts[-1],
@@ -241,8 +280,9 @@ def main():
             "peak": roofline.MI355X_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / roofline.MI355X_HBM_GBS,
-            "traffic": None,
+            "traffic": None if tpe is None else tpe * evals,
             "algorithmic_bytes_per_launch": by,
+            "evals_per_launch": evals,
             "kernel_ms": k_ms,
             "achieved_tflops": fl / (k_ms * 1e-3) / 1e12,
         },

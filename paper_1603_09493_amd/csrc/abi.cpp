@@ -858,7 +858,7 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
   meshes.erase(std::unique(meshes.begin(), meshes.end()), meshes.end());
   if (meshes.size() != 1) return fail(c, BPM_EINVAL, "bpm_autotune: tunes runs of one mesh group");
   double best_t = INFINITY;
-  int best_g = -1;
+  int best_g = 0;
   for (int q = 0; q < n_cand; ++q) {
     bpm_run_opts p = *o;
     p.wg_per_group = cand[q] > 0 ? cand[q] : -cand[q];
@@ -881,7 +881,8 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
       best_g = cand[q] > 0 ? c->run_G : -c->run_G;
     }
   }
-  if (best_g < 0) return fail(c, BPM_EINVAL, "bpm_autotune: no candidate could run");
+  // a winning 512-thread candidate is reported negative, so test the time, not the sign
+  if (!std::isfinite(best_t) || best_g == 0) return fail(c, BPM_EINVAL, "bpm_autotune: no candidate could run");
   *best = best_g;
   const auto key = tune_key(nmax, (int)c->insts.size(), o->precision);
   c->tune[key] = best_g;

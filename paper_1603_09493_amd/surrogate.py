@@ -8,7 +8,7 @@ once; the batched solver stays the judge of every pick.
 
 Design vector (12): d, t_soft, t_hard, Ms_soft, Ms_hard, K_soft, K_hard, A_int, psi, B_peak,
 alpha, t_rise -- inputs.DESIGN_LO/HI give the ranges.  Network inputs are the designs scaled to
-[-1, 1]; targets are z-scored B_sw, z-scored log t_sw and the switched flag (masked regression
+[-1, 1]; targets are z-scored log B_sw, z-scored log t_sw and the switched flag (masked regression
 where the design did not switch).
 """
 from __future__ import annotations
@@ -51,31 +51,58 @@ class Labels:
 
 
 def label_designs(ctx: bpm.Context, x: np.ndarray, t_end: float = 0.5e-9, precision: int = 32,
-                  mesh_seed0: int = 0, clear: bool = True) -> Labels:
-    """Runs every design (rows of x) as one island in one batched launch."""
-    if clear:
-        ctx.clear_instances()
-    ids = []
-    for q, row in enumerate(np.asarray(x, dtype=np.float64)):
-        mesh, mat, fld = I.design_inputs(row, seed=mesh_seed0 + q)
-        mid = ctx.mesh_add(mesh)
-        ids.append(ctx.instance_add(mid, mat, fld))
-    t0 = time.perf_counter()
-    ctx.run(t_end=t_end, precision=precision, rtol=1e-5 if precision == 32 else 1e-6)
-    ctx.sync()
-    wall = time.perf_counter() - t0
-    res = ctx.results(ids)
-    sw = np.array([bool(r["switched"]) for r in res])
-    tsw = np.array([r["t_sw"] for r in res])
-    bsw = np.array([r["B_sw"] for r in res])
-    st = np.array([r["status"] for r in res])
+                  mesh_seed: int = 0, clear: bool = True, chunk: int = 96, work: float = 2.5e8) -> Labels:
+    """Runs every design (rows of x) as one island, in batched launches of designs of similar size,
+    each launch holding at most `chunk` designs and at most `work` summed N^2 (so that the launcher
+    can give large islands several workgroups).  Every design is meshed with the same jitter seed,
+    so that its mesh (and label) is a function of the design alone."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    built = []
+    for row in x:
+        mesh, mat, fld = I.design_inputs(row, seed=mesh_seed)
+        built.append((mesh, mat, fld))
+    order = np.argsort([b[0].n for b in built], kind="stable")
+    sw = np.zeros(n, bool)
+    tsw = np.full(n, np.nan)
+    bsw = np.full(n, np.nan)
+    st = np.zeros(n, np.int64)
+    kernel_ms = 0.0
+    wall = 0.0
+    keep = 2 if precision == 32 else 1
+    chunks, cur, w = [], [], 0.0
+    for q in order:
+        nq2 = float(built[q][0].n) ** 2
+        if cur and (len(cur) >= chunk or w + nq2 > work):
+            chunks.append(cur)
+            cur, w = [], 0.0
+        cur.append(q)
+        w += nq2
+    if cur:
+        chunks.append(cur)
+    for c0, idx in enumerate(chunks):
+        if clear or c0 > 0:
+            ctx.clear_instances()
+        ids = []
+        for q in idx:
+            mesh, mat, fld = built[q]
+            mid = ctx.mesh_add(mesh, keep=keep)
+            ids.append(ctx.instance_add(mid, mat, fld))
+        t0 = time.perf_counter()
+        ctx.run(t_end=t_end, precision=precision, rtol=1e-5 if precision == 32 else 1e-6)
+        ctx.sync()
+        wall += time.perf_counter() - t0
+        kernel_ms += ctx.last_run_info()["kernel_ms"]
+        for q, r in zip(idx, ctx.results(ids)):
+            sw[q], tsw[q], bsw[q], st[q] = bool(r["switched"]), r["t_sw"], r["B_sw"], r["status"]
     ok = sw & np.isfinite(tsw) & np.isfinite(bsw) & (tsw > 0)
     return Labels(switched=ok, B_sw=np.where(ok, bsw, np.nan), t_sw=np.where(ok, tsw, np.nan), status=st,
-                  kernel_ms=ctx.last_run_info()["kernel_ms"], wall_s=wall)
+                  kernel_ms=kernel_ms, wall_s=wall)
 
 
 @dataclasses.dataclass
 class TargetScaler:
+    """z-scores of log B_sw and log t_sw (a squared error in log B_sw is a relative error)."""
     b_mu: float
     b_sd: float
     t_mu: float
@@ -83,20 +110,20 @@ class TargetScaler:
 
     @staticmethod
     def fit(lab: Labels) -> "TargetScaler":
-        b = lab.B_sw[lab.switched]
+        b = np.log(lab.B_sw[lab.switched])
         t = np.log(lab.t_sw[lab.switched])
         return TargetScaler(float(b.mean()), float(b.std() + 1e-12), float(t.mean()), float(t.std() + 1e-12))
 
     def targets(self, lab: Labels):
         T = np.zeros((lab.switched.size, 3), np.float32)
         m = lab.switched
-        T[m, 0] = (lab.B_sw[m] - self.b_mu) / self.b_sd
+        T[m, 0] = (np.log(lab.B_sw[m]) - self.b_mu) / self.b_sd
         T[m, 1] = (np.log(lab.t_sw[m]) - self.t_mu) / self.t_sd
         T[:, 2] = m.astype(np.float32)
         return T, m.astype(np.uint8)
 
     def B_of(self, y0):
-        return self.b_mu + self.b_sd * np.asarray(y0, dtype=np.float64)
+        return np.exp(self.b_mu + self.b_sd * np.asarray(y0, dtype=np.float64))
 
 
 def train(net: bpm.Mlp, X: np.ndarray, T: np.ndarray, mask: np.ndarray, epochs: int = 200, batch: int = 512,

@@ -283,3 +283,29 @@ def test_symmetric_demag_product_matches_full(ctx, cfg0, oracle_mod):
     assert abs(r_sym[0]["t_sw"] / ro[0]["t_sw"] - 1) <= 0.01
     assert abs(r_sym[0]["B_sw"] / ro[0]["B_sw"] - 1) <= 0.01
     assert abs(r_sym[0]["t_sw"] / r_full[0]["t_sw"] - 1) <= 1e-3
+
+
+def test_autotune_picks_fastest_and_run_uses_it(ctx):
+    """The launch-shape tuner returns the fastest candidate (negative = 512-thread workgroups), and
+    a run that names no shape uses the tuned one."""
+    mesh, mats, flds, offs = I.patch_workload(n_target=500)
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh)
+    ids = [ctx.instance_add(mid, m, f, offset=o) for m, f, o in zip(mats, flds, offs)]
+    ctx.couple_dipoles(ids)
+    cands = [4, 16, -16]
+    _print_case("autotune", n=mesh.n, cands=cands)
+    best, ms = ctx.autotune(cands, probe_attempts=20, t_end=1e-11, precision=32, rtol=1e-5)
+    assert np.all(np.isfinite(ms)) and np.all(ms > 0)
+    assert best == cands[int(np.argmin(ms))]
+    ctx.run(t_end=2e-13, precision=32, rtol=1e-5)
+    ctx.sync()
+    assert ctx.last_run_info()["wg_per_group"] == abs(best)
+    assert ctx.last_run_layout()["threads"] == (512 if best < 0 else 256)
+    # a candidate list of 512-thread shapes only still tunes (the winner is reported negative)
+    best2, ms2 = ctx.autotune([-8], probe_attempts=10, t_end=1e-11, precision=32, rtol=1e-5)
+    assert best2 == -8 and np.isfinite(ms2[0])
+    ctx.run(t_end=2e-13, precision=32, rtol=1e-5)
+    ctx.sync()
+    assert ctx.last_run_info()["wg_per_group"] == 8 and ctx.last_run_layout()["threads"] == 512
+    assert all(r["status"] == 0 for r in ctx.results(ids))

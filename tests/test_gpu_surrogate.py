@@ -54,8 +54,8 @@ def test_surrogate_trains_and_screens_better_than_random():
     xr = I.sample_designs(4000, seed=77, fixed_alpha_rise=False)
     xr = xr[SG.stability(xr) >= min_stab][:48]
     assert xr.shape[0] == 48
-    lab_p = SG.label_designs(ctx, xp, t_end=t_end, mesh_seed0=5000)
-    lab_r = SG.label_designs(ctx, xr, t_end=t_end, mesh_seed0=6000)
+    lab_p = SG.label_designs(ctx, xp, t_end=t_end)
+    lab_r = SG.label_designs(ctx, xr, t_end=t_end)
     hit_p, hit_r = lab_p.switched.mean(), lab_r.switched.mean()
     print(f"[surrogate] screen 200k in {secs*1e3:.1f} ms; solver-verified switching: picks {hit_p:.2f} "
           f"vs random {hit_r:.2f}", flush=True)
