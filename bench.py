@@ -46,7 +46,7 @@ def cpu_baseline_patch(mesh, mats, flds, offs, t_sample=2e-12):
                       f"({res[0]['n_accept']} DP5 steps, {wall:.1f} s wall), rate extrapolated"}
 
 
-def surrogate_leg(n_train=448, n_test=128, t_end=0.3e-9, n_cand=1_000_000, k=10_000, epochs=300):
+def surrogate_leg(n_train=1536, n_test=256, t_end=0.3e-9, n_cand=1_000_000, k=10_000, epochs=120, log=None):
     """Label designs with the batched FP32 solver, train the MLP with the library's kernels,
     report the held-out switching-field error and time a 1M-candidate screening round."""
     import numpy as np
@@ -57,7 +57,7 @@ def surrogate_leg(n_train=448, n_test=128, t_end=0.3e-9, n_cand=1_000_000, k=10_
     from paper_1603_09493_amd import surrogate as SG
     ctx = bpm.Context(0)
     x = I.sample_designs(n_train + n_test, seed=12, fixed_alpha_rise=False)
-    lab = SG.label_designs(ctx, x, t_end=t_end)
+    lab = SG.label_designs(ctx, x, t_end=t_end, progress=log)
     solver_designs_per_s = x.shape[0] / lab.wall_s
     X = SG.scale(x).astype(np.float32)
     tr, te = slice(0, n_train), slice(n_train, None)
@@ -289,7 +289,7 @@ def main():
     }
     ctx.close()
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg()
+        out["surrogate"] = surrogate_leg(log=log)
     if args.copy_calib:
         out["copy_calibration"] = copy_calibration()
     if args.batch > 0:

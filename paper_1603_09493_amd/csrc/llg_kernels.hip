@@ -199,6 +199,25 @@ __device__ __forceinline__ void applied_B(const InstConst& c, double t, double x
   bz = amp * c.dir[2] + c.B_ext[2];
 }
 
+// The same field with the profile evaluated in FP32 (positions and times stay FP64), for FP32
+// runs: its rounding (~1e-7) is far below their tolerance.
+__device__ __forceinline__ void applied_B_f32(const InstConst& c, double t, double x, double y,
+                                              float& bx, float& by, float& bz) {
+  float amp = (float)(c.B_peak * rise_of(c, t));
+  if (c.fkind == BPM_FIELD_POLE) {
+    const float il = (float)(1.0 / c.L_grad);
+    const float sx = (float)(x - c.x_off[0] - c.v[0] * t) * il;
+    const float sy = (float)(y - c.x_off[1] - c.v[1] * t) * il;
+    const float hw = (float)(0.5 * c.W_pole) * il;
+    const float fx = 0.5f * (1.0f - tanhf(sx));
+    const float fy = 0.5f * (tanhf(sy + hw) - tanhf(sy - hw));
+    amp *= fx * fy;
+  }
+  bx = amp * (float)c.dir[0] + (float)c.B_ext[0];
+  by = amp * (float)c.dir[1] + (float)c.B_ext[1];
+  bz = amp * (float)c.dir[2] + (float)c.B_ext[2];
+}
+
 // ---------------------------------------------------------------------------------------------
 // control state, replicated per workgroup in LDS
 // ---------------------------------------------------------------------------------------------
@@ -297,10 +316,6 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
   const GLB real* __restrict__ ysrc = glb(ysrc_);
   GLB real* __restrict__ yexg = glb(g.yex);
   GLB real* __restrict__ bg = glb(g.b);
-  if (c.any_coupled) {
-    for (int q = threadIdx.x; q < g.R * 3; q += BS) c.accL[q / 3][q % 3] = 0.0;
-    __syncthreads();
-  }
   // every (instance, owned node) pair in one pass
   for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
     const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
@@ -309,7 +324,6 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
     const GLB real* y = ysrc + (size_t)r * 3 * n;
     real ex0 = 0, ex1 = 0, ex2 = 0, bb = 0;
     const int qa = cs.rp[k], qb = cs.rp[k + 1];
-    const real own0 = xld<kX>(y + i), own1 = xld<kX>(y + n + i), own2 = xld<kX>(y + 2 * n + i);
     constexpr int kGather = Gather<real>::W;
     for (int q0 = qa; q0 < qb; q0 += kGather) {
       // all gathers of the row in flight at once (masked entries read the node itself)
@@ -340,20 +354,6 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
     yex[n + i] = ex1;
     yex[2 * n + i] = ex2;
     xst<kX>(bg + (size_t)r * ldS + i, bb);
-    if (c.coupled[r]) {
-      const double w = (double)(cs.lay[k] ? Ms1 : Ms0) * (double)cs.V[k];
-      atomicAdd(&c.accL[r][0], w * (double)own0);
-      atomicAdd(&c.accL[r][1], w * (double)own1);
-      atomicAdd(&c.accL[r][2], w * (double)own2);
-    }
-  }
-  if (c.any_coupled) {
-    __syncthreads();
-    for (int q = threadIdx.x; q < g.R * 3; q += BS) {
-      const int r = q / 3, d = q % 3;
-      if (c.coupled[r] && c.active[c.isys[r]])
-        atomicAdd(&P.mom_acc[((size_t)(g.inst0 + r) * 3 + ev % 3) * 3 + d], c.accL[r][d]);
-    }
   }
 }
 
@@ -456,6 +456,7 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
     __syncthreads();
     if (U <= 3) demag_rows<real, BS, kSL, kX, 3, 4>(g, i0, nr, bL, SL, part, rb, rn);
     else if (U <= 6) demag_rows<real, BS, kSL, kX, 6, 2>(g, i0, nr, bL, SL, part, rb, rn);
+    else if (U <= 9) demag_rows<real, BS, kSL, kX, 9, 2>(g, i0, nr, bL, SL, part, rb, rn);
     else demag_rows<real, BS, kSL, kX, 12, 1>(g, i0, nr, bL, SL, part, rb, rn);   // several rounds beyond 12
   }
 }
@@ -540,6 +541,61 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
   }
 }
 
+// Dipole moments of coupled instances, mu_I = sum_i Ms_L(i) V_i y_i of a stage input y: every
+// writer of a stage input adds its nodes' share into c.mom (LDS atomics, zeroed by the caller)
+// and then into the global slot of the evaluation that reads that input.
+__device__ __forceinline__ void mom_add(Ctl& c, const InstConst& ic, int r, int L, double V, double y0,
+                                        double y1, double y2) {
+  if (!c.coupled[r]) return;
+  const double w = ic.Ms[L] * V;
+  atomicAdd(&c.mom[r][0], w * y0);
+  atomicAdd(&c.mom[r][1], w * y1);
+  atomicAdd(&c.mom[r][2], w * y2);
+}
+
+// field of the coupled neighbours at each coupled instance from the moments in c.mom
+template <int BS>
+__device__ __forceinline__ void dipole_fields(Ctl& c, const InstConst* icL, const double* dipL, int R) {
+  if (dipL) {
+    // one (instance, component) per thread from the pair geometry staged at launch start
+    for (int q = threadIdx.x; q < R * 3; q += BS) {
+      const int J = q / 3, d = q - 3 * J;
+      double B = 0.0;
+      if (c.coupled[J]) {
+        for (int I = 0; I < R; ++I) {
+          if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
+          const double* gJI = dipL + ((size_t)J * R + I) * 4;
+          const double* mu = c.mom[I];
+          const double mr = mu[0] * gJI[0] + mu[1] * gJI[1] + mu[2] * gJI[2];
+          B += gJI[3] * (3.0 * mr * gJI[d] - mu[d]);
+        }
+      }
+      c.Bdip[J][d] = B;
+    }
+  } else {
+    for (int J = threadIdx.x; J < R; J += BS) {
+      double B0 = 0.0, B1 = 0.0, B2 = 0.0;
+      if (c.coupled[J]) {
+        const InstConst& cj = icL[J];
+        for (int I = 0; I < R; ++I) {
+          if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
+          const InstConst& ci = icL[I];
+          const double* mu = c.mom[I];
+          const double d0 = cj.off[0] - ci.off[0], d1 = cj.off[1] - ci.off[1], d2 = cj.off[2] - ci.off[2];
+          const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          const double e0 = d0 / rr, e1 = d1 / rr, e2 = d2 / rr;
+          const double mr = mu[0] * e0 + mu[1] * e1 + mu[2] * e2;
+          const double f = kMu0 / (4.0 * kPi * rr * rr * rr);
+          B0 += f * (3.0 * mr * e0 - mu[0]);
+          B1 += f * (3.0 * mr * e1 - mu[1]);
+          B2 += f * (3.0 * mr * e2 - mu[2]);
+        }
+      }
+      c.Bdip[J][0] = B0; c.Bdip[J][1] = B1; c.Bdip[J][2] = B2;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // phase C: effective field, LLG right-hand side, next stage input, reductions
 // ---------------------------------------------------------------------------------------------
@@ -612,10 +668,17 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
   const real cd = -(real)kMu0 / Vi;
   Bx += cd * dx; By += cd * dy; Bz += cd * dz;
   // Zeeman (+ dipoles)
-  double zx, zy, zz;
-  applied_B(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
-  if (c.coupled[r]) { zx += c.Bdip[r][0]; zy += c.Bdip[r][1]; zz += c.Bdip[r][2]; }
-  Bx += (real)zx; By += (real)zy; Bz += (real)zz;
+  if constexpr (sizeof(real) == 4) {
+    float zx, zy, zz;
+    applied_B_f32(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
+    if (c.coupled[r]) { zx += (float)c.Bdip[r][0]; zy += (float)c.Bdip[r][1]; zz += (float)c.Bdip[r][2]; }
+    Bx += zx; By += zy; Bz += zz;
+  } else {
+    double zx, zy, zz;
+    applied_B(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
+    if (c.coupled[r]) { zx += c.Bdip[r][0]; zy += c.Bdip[r][1]; zz += c.Bdip[r][2]; }
+    Bx += (real)zx; By += (real)zy; Bz += (real)zz;
+  }
   // LLG: dm/dt = -gp [ m x B + alpha m x (m x B) ]
   const real cx = my * Bz - mz * By, cy = mz * Bx - mx * Bz, cz = mx * By - my * Bx;
   const real dx2 = my * cz - mz * cy, dy2 = mz * cx - mx * cz, dz2 = mx * cy - my * cx;
@@ -636,6 +699,7 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
     const real ha = (real)(h * kA[s + 1][s]);
     v[0] += ha * kx; v[1] += ha * ky; v[2] += ha * kz;
     xst<kX>(yn + i, v[0]); xst<kX>(yn + n + i, v[1]); xst<kX>(yn + 2 * n + i, v[2]);
+    if (s >= 1) mom_add(c, ic, r, L, (double)Vi, (double)v[0], (double)v[1], (double)v[2]);
     if (s == 5) {
       // observables of the normalised candidate
       const double nr = sqrt((double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2]);
@@ -679,50 +743,9 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
   const int nown = i1 - i0;
   const GLB real* ysrc = glb(ysrc_);
   GLB real* ydst = glb(ydst_);
-  // dipole fields of coupled instances from the moments of this stage
-  if (c.any_coupled) {
-    for (int q = threadIdx.x; q < g.R * 3; q += BS)
-      c.mom[q / 3][q % 3] = acc_ld(&P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + ev % 3) * 3 + q % 3]);
-    __syncthreads();
-    if (dipL) {
-      // one (instance, component) per thread from the pair geometry staged at launch start
-      for (int q = threadIdx.x; q < g.R * 3; q += BS) {
-        const int J = q / 3, d = q - 3 * J;
-        double B = 0.0;
-        if (c.coupled[J]) {
-          for (int I = 0; I < g.R; ++I) {
-            if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
-            const double* gJI = dipL + ((size_t)J * g.R + I) * 4;
-            const double* mu = c.mom[I];
-            const double mr = mu[0] * gJI[0] + mu[1] * gJI[1] + mu[2] * gJI[2];
-            B += gJI[3] * (3.0 * mr * gJI[d] - mu[d]);
-          }
-        }
-        c.Bdip[J][d] = B;
-      }
-    } else {
-      for (int J = threadIdx.x; J < g.R; J += BS) {
-        double B0 = 0.0, B1 = 0.0, B2 = 0.0;
-        if (c.coupled[J]) {
-          const InstConst& cj = icL[J];
-          for (int I = 0; I < g.R; ++I) {
-            if (I == J || !c.coupled[I] || c.isys[I] != c.isys[J]) continue;
-            const InstConst& ci = icL[I];
-            const double* mu = c.mom[I];
-            const double d0 = cj.off[0] - ci.off[0], d1 = cj.off[1] - ci.off[1], d2 = cj.off[2] - ci.off[2];
-            const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const double e0 = d0 / rr, e1 = d1 / rr, e2 = d2 / rr;
-            const double mr = mu[0] * e0 + mu[1] * e1 + mu[2] * e2;
-            const double f = kMu0 / (4.0 * kPi * rr * rr * rr);
-            B0 += f * (3.0 * mr * e0 - mu[0]);
-            B1 += f * (3.0 * mr * e1 - mu[1]);
-            B2 += f * (3.0 * mr * e2 - mu[2]);
-          }
-        }
-        c.Bdip[J][0] = B0; c.Bdip[J][1] = B1; c.Bdip[J][2] = B2;
-      }
-    }
-  }
+  // moments of the next stage input (written below) of coupled instances
+  if (c.any_coupled)
+    for (int q = threadIdx.x; q < g.R * 3; q += BS) c.mom[q / 3][q % 3] = 0.0;
   if (s >= 5) {
     for (int q = threadIdx.x; q < g.R * 6; q += BS) c.accL[q / 6][q % 6] = 0.0;
     for (int q = threadIdx.x; q < g.nsys; q += BS) c.errL[q] = 0.0;
@@ -733,6 +756,14 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
     const int sl = c.isys[r];
     if (!c.active[sl]) continue;
     pair_C<real, kL, kX>(g, P, c, icL[r], s, r, k, i0, sl, ysrc, ydst, cs);
+  }
+  if (c.any_coupled && s >= 1 && s < 6) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < g.R * 3; q += BS) {
+      const int r = q / 3, d = q % 3;
+      if (c.coupled[r] && c.active[c.isys[r]])
+        atomicAdd(&P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 1) % 3) * 3 + d], c.mom[r][d]);
+    }
   }
   if (s >= 5) {
     __syncthreads();
@@ -759,9 +790,19 @@ __device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunPa
                                            const Csr<real, kL>& cs) {
   phase_A<real, BS, kL, kX>(g, P, c, icL, i0, i1, ysrc, ev, cs);
   group_sync<kX>(gs);
+  // dipole moments of this stage input (complete after the barrier): loaded now, consumed after
+  // the demag product, so that their latency hides behind it
+  const bool mq = c.any_coupled && threadIdx.x < g.R * 3;
+  double mv = 0.0;
+  if (mq) mv = acc_ld(&P.mom_acc[((size_t)(g.inst0 + threadIdx.x / 3) * 3 + ev % 3) * 3 + threadIdx.x % 3]);
   if (SL) phase_B<real, BS, true, kX>(g, c, i0, i1, bL, SL, part, RB);
   else if (!kX && g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real, BS>(g, c, bL, RB);
   else phase_B<real, BS, false, kX>(g, c, i0, i1, bL, nullptr, part, RB);
+  if (c.any_coupled) {
+    if (mq) c.mom[threadIdx.x / 3][threadIdx.x % 3] = mv;
+    __syncthreads();
+    dipole_fields<BS>(c, icL, dipL, g.R);
+  }
   group_sync<kX>(gs);
   phase_C<real, kFixed, BS, kL, kX>(g, P, c, icL, dipL, i0, i1, s, ysrc, ydst, it, ev, cs);
   group_sync<kX>(gs);
@@ -885,6 +926,10 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
   __syncthreads();
   for (int q = threadIdx.x; q < g.R * 5; q += BS)
     atomicAdd(&P.obs_acc[((size_t)(g.inst0 + q / 5) * 3 + 2) * 6 + q % 5], c.accL[q / 5][q % 5]);
+  // dipole moments of m0 (the sums Ms V m of the observables) for the first evaluation
+  if (c.any_coupled)
+    for (int q = threadIdx.x; q < g.R * 3; q += BS)
+      if (c.coupled[q / 3]) atomicAdd(&P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + 0) * 3 + q % 3], c.accL[q / 3][2 + q % 3]);
   group_sync<kX>(gs);
   // One call site of the field evaluation (its code is large): the evaluation of stage 0 of the
   // prologue is the first pass of the loop, then stages 1..6 of every attempt.
@@ -906,9 +951,10 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         for (int sl = threadIdx.x; sl < g.nsys; sl += BS) acc_st(&P.err_acc[(size_t)(g.sys0 + sl) * 3 + (it + 2) % 3], 0.0);
       }
     }
-    if (s >= 1 && lead && c.any_coupled)
+    // the moment slot of the next evaluation, filled by the writers of its stage input
+    if (lead && c.any_coupled)
       for (int r = threadIdx.x; r < g.R; r += BS)
-        for (int d = 0; d < 3; ++d) acc_st(&P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 2) % 3) * 3 + d], 0.0);
+        for (int d = 0; d < 3; ++d) acc_st(&P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 1) % 3) * 3 + d], 0.0);
     {
       const real* src = (s & 1) ? ys1 : ys0;
       real* dst = (s & 1) ? ys0 : ys1;
@@ -926,19 +972,31 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         if (vh <= 0.0) { c.crossed[r] = 1; c.tsw[r] = 0.0; }
         if (lead) save_sample<real, BS>(g, P, c, icL, r, 0.0, 0.0, 0.0, ob);
       }
+      for (int q = threadIdx.x; q < g.R * 3; q += BS) c.mom[q / 3][q % 3] = 0.0;
       __syncthreads();
       plan_attempt<kFixed, BS>(P, c, g.nsys, nfix);
       __syncthreads();
       for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
-        const int r = it2 / nown, i = i0 + (it2 - r * nown);
+        const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
         const int sl = c.isys[r];
         if (!c.active[sl]) continue;
         const real ha = (real)(c.h[sl] * kA[1][0]);
         const GLB real* m = mg + (size_t)r * st3;
         const GLB real* k0 = kg + (size_t)r * 7 * st3;
         GLB real* yn = glb(ys1) + (size_t)r * st3;
+        real v[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) xst<kX>(yn + d * n + i, m[d * n + i] + ha * k0[d * n + i]);
+        for (int d = 0; d < 3; ++d) {
+          v[d] = m[d * n + i] + ha * k0[d * n + i];
+          xst<kX>(yn + d * n + i, v[d]);
+        }
+        mom_add(c, icL[r], r, cs.lay[k], (double)cs.V[k], (double)v[0], (double)v[1], (double)v[2]);
+      }
+      if (c.any_coupled) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < g.R * 3; q += BS)
+          if (c.coupled[q / 3] && c.active[c.isys[q / 3]])
+            atomicAdd(&P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + ev % 3) * 3 + q % 3], c.mom[q / 3][q % 3]);
       }
       group_sync<kX>(gs);
       s = 1;
@@ -1011,12 +1069,13 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         if (dev > c.maxdev[sl]) c.maxdev[sl] = dev;
       }
     }
+    for (int q = threadIdx.x; q < g.R * 3; q += BS) c.mom[q / 3][q % 3] = 0.0;
     plan_attempt<kFixed, BS>(P, c, g.nsys, nfix);
     __syncthreads();
     // accepted: m <- y / |y| (the stage-7 input), k1 <- k7; then the stage-2 input of the next
     // attempt of every active system, from the values already in registers
     for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
-      const int r = it2 / nown, i = i0 + (it2 - r * nown);
+      const int r = it2 / nown, k = it2 - r * nown, i = i0 + k;
       const int sl = c.isys[r];
       const bool acc = c.accepted[sl], act = c.active[sl];
       if (!acc && !act) continue;
@@ -1039,9 +1098,20 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
       if (act) {
         const real ha = (real)(c.h[sl] * kA[1][0]);
         GLB real* yn = glb(ys1) + (size_t)r * st3;
+        real v[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) xst<kX>(yn + d * n + i, mv[d] + ha * kv[d]);
+        for (int d = 0; d < 3; ++d) {
+          v[d] = mv[d] + ha * kv[d];
+          xst<kX>(yn + d * n + i, v[d]);
+        }
+        mom_add(c, icL[r], r, cs.lay[k], (double)cs.V[k], (double)v[0], (double)v[1], (double)v[2]);
       }
+    }
+    if (c.any_coupled) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < g.R * 3; q += BS)
+        if (c.coupled[q / 3] && c.active[c.isys[q / 3]])
+          atomicAdd(&P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + ev % 3) * 3 + q % 3], c.mom[q / 3][q % 3]);
     }
     group_sync<kX>(gs);
     ++it;

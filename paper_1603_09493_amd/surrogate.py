@@ -51,11 +51,13 @@ class Labels:
 
 
 def label_designs(ctx: bpm.Context, x: np.ndarray, t_end: float = 0.5e-9, precision: int = 32,
-                  mesh_seed: int = 0, clear: bool = True, chunk: int = 96, work: float = 2.5e8) -> Labels:
+                  mesh_seed: int = 0, clear: bool = True, chunk: int = 96, work: float = 2.5e8,
+                  progress=None) -> Labels:
     """Runs every design (rows of x) as one island, in batched launches of designs of similar size,
     each launch holding at most `chunk` designs and at most `work` summed N^2 (so that the launcher
     can give large islands several workgroups).  Every design is meshed with the same jitter seed,
-    so that its mesh (and label) is a function of the design alone."""
+    so that its mesh (and label) is a function of the design alone.  `progress` (optional) receives
+    one line per launch."""
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     built = []
@@ -95,6 +97,9 @@ def label_designs(ctx: bpm.Context, x: np.ndarray, t_end: float = 0.5e-9, precis
         kernel_ms += ctx.last_run_info()["kernel_ms"]
         for q, r in zip(idx, ctx.results(ids)):
             sw[q], tsw[q], bsw[q], st[q] = bool(r["switched"]), r["t_sw"], r["B_sw"], r["status"]
+        if progress is not None:
+            progress(f"labelled chunk {c0 + 1}/{len(chunks)}: {len(idx)} designs, "
+                     f"{ctx.last_run_info()['kernel_ms']:.0f} ms")
     ok = sw & np.isfinite(tsw) & np.isfinite(bsw) & (tsw > 0)
     return Labels(switched=ok, B_sw=np.where(ok, bsw, np.nan), t_sw=np.where(ok, tsw, np.nan), status=st,
                   kernel_ms=kernel_ms, wall_s=wall)
@@ -163,12 +168,21 @@ def predict(net: bpm.Mlp, X: np.ndarray) -> np.ndarray:
     return Yd.cpu().numpy()
 
 
+def bsw_predicted(sc: TargetScaler, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Switching field predicted for designs X (scaled) from the network outputs Y.  B_sw is the
+    applied field at the island at t_sw; for the uniform ramped field of the design workload that
+    is B_peak * min(t_sw / t_rise, 1), taken here with the predicted t_sw (output 1)."""
+    x = unscale(X)
+    t = np.exp(sc.t_mu + sc.t_sd * np.asarray(Y[:, 1], dtype=np.float64))
+    return x[:, 9] * np.minimum(t / x[:, 11], 1.0)
+
+
 def bsw_error(net: bpm.Mlp, sc: TargetScaler, X: np.ndarray, lab: Labels):
     """Mean and 95th percentile of |relative error| of the predicted switching field over the
     designs that switched."""
     Y = predict(net, X)
     m = lab.switched
-    rel = np.abs(sc.B_of(Y[m, 0]) / lab.B_sw[m] - 1.0)
+    rel = np.abs(bsw_predicted(sc, X[m], Y[m]) / lab.B_sw[m] - 1.0)
     return float(rel.mean()), float(np.percentile(rel, 95)), Y
 
 
