@@ -84,7 +84,7 @@ def surrogate_leg(n_train=1536, n_test=256, t_end=0.3e-9, n_cand=1_000_000, k=10
             "valid_at_2pct": bool(err <= 0.02)}
 
 
-def batch_leg(n_islands=4096, t_end=1e-11, steps=1):
+def batch_leg(n_islands=4096, t_end=1e-11, steps=1, log=None):
     """Batched independent islands of uneven size (designs uniform in the batched ranges, N
     proportional to volume in [300, 3000], FP32 demag only), one persistent launch, per-island
     adaptive steps."""
@@ -100,6 +100,8 @@ def batch_leg(n_islands=4096, t_end=1e-11, steps=1):
         ids.append(ctx.instance_add(mid, mat, fld))
         sizes.append(mesh.n)
         nnzs.append(int(ctx.mesh_get_assembly(mid)["rowptr"][-1]) if q < 64 else None)
+        if log and q % 1024 == 1023:
+            log(f"batch: {q + 1} islands set up")
     setup_s = time.perf_counter() - t0
     ctx.run(t_end=t_end, precision=32, rtol=1e-5)      # warm-up
     ctx.sync()
@@ -121,6 +123,50 @@ def batch_leg(n_islands=4096, t_end=1e-11, steps=1):
             "attempts_min": int(min(att)), "attempts_max": int(max(att)),
             "achieved_GBs": by / (info["kernel_ms"] * 1e-3) / 1e9,
             "status_ok": int(sum(1 for r in res if r["status"] == 0))}
+
+
+def heun_leg(n_designs=64, realizations=1024, steps=40, dt=5e-15, temperature=300.0, log=None):
+    """Thermal workload: n_designs patch-island meshes (the patch island, one mesh seed each), each
+    with `realizations` Philox streams, a static stray field U(0.3, 0.6) T along -z at 300 K,
+    stochastic Heun at fixed dt, FP32.  Reports realization-ns/s and the FP32 matrix-core use of
+    the demag products (2 N^2 R flops per field evaluation, two evaluations per step)."""
+    import dataclasses
+    import numpy as np
+    from paper_1603_09493_amd import bpm, roofline
+    from paper_1603_09493_amd import inputs as I
+    ctx = bpm.Context(0)
+    rng = np.random.default_rng(3)
+    base_mesh, mats, flds, _ = I.patch_workload()
+    mat0 = mats[0]
+    n_total, flops_per_step = 0, 0.0
+    t0 = time.perf_counter()
+    for dsg in range(n_designs):
+        mesh = base_mesh if dsg == 0 else I.patch_workload(seed=1 + dsg)[0]
+        mid = ctx.mesh_add(mesh, keep=2)
+        B = float(rng.uniform(0.3, 0.6))
+        fld = I.Field(kind=I.FIELD_UNIFORM, B_peak=B, dir=(0.0, 0.0, -1.0), t_rise=0.0)
+        for r in range(realizations):
+            ctx.instance_add(mid, mat0, fld, seed=(3 << 48) | (dsg << 20) | r)
+        n_total += mesh.n
+        flops_per_step += 2 * 2.0 * mesh.n * mesh.n * realizations
+        if log and dsg % 16 == 15:
+            log(f"heun: {dsg + 1} designs set up")
+    setup_s = time.perf_counter() - t0
+    kw = dict(t_end=steps * dt, precision=32, integrator=bpm.HEUN, dt_fixed=dt, temperature=temperature)
+    ctx.run(**dict(kw, t_end=2 * dt))      # warm-up (graph capture, first touch)
+    ctx.sync()
+    _device_sync()
+    t0 = time.perf_counter()
+    ctx.run(**kw)
+    ctx.sync()
+    wall = time.perf_counter() - t0
+    k_ms = ctx.last_run_info()["kernel_ms"]
+    ctx.close()
+    tf = flops_per_step * steps / (k_ms * 1e-3) / 1e12
+    return {"designs": n_designs, "realizations": realizations, "nodes_per_island_mean": n_total / n_designs,
+            "steps": steps, "dt_fs": dt * 1e15, "value": n_designs * realizations * steps * dt * 1e9 / wall,
+            "unit": "realization-ns/s", "kernel_ms": k_ms, "setup_s": setup_s,
+            "demag_gemm_tflops": tf, "demag_gemm_frac_fp32_mfma": tf / roofline.MI355X_FP32_TFLOPS}
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "dp5_kernel_patch_counters.txt")
@@ -183,6 +229,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="also run a 512 MiB device copy (profiling)")
     ap.add_argument("--batch", type=int, default=0, help="also run N batched uneven islands (0 = skip)")
     ap.add_argument("--batch-t-end", type=float, default=1e-11)
+    ap.add_argument("--heun", type=int, default=0, help="also run the thermal workload with N designs (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -293,7 +340,9 @@ def main():
     if args.copy_calib:
         out["copy_calibration"] = copy_calibration()
     if args.batch > 0:
-        out["batch"] = batch_leg(args.batch, args.batch_t_end)
+        out["batch"] = batch_leg(args.batch, args.batch_t_end, log=log)
+    if args.heun > 0:
+        out["heun"] = heun_leg(args.heun, log=log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_patch(mesh, mats, flds, offs)
     print(json.dumps(out), flush=True)

@@ -70,7 +70,9 @@ typedef struct {
  * S (energy (mu0/2) b^T S b of the nodal charges b) is either copied from S_host ([n][n] FP64,
  * row-major) or, when S_host is NULL, assembled on the GPU from Gaussian charge blobs of
  * standard deviation demag_beta * V_tet^(1/3) at the tet centroids (demag_beta <= 0 selects the
- * default 0.29166..., the blob whose self-energy equals a uniformly charged ball).
+ * default 0.29166..., the blob whose self-energy equals a uniformly charged ball).  The stored
+ * operator is made exactly symmetric, S <- (S + S^T) / 2 (an energy operator is symmetric by
+ * definition; the kernels read either triangle).
  * Errors: BPM_EINVAL for an empty or inconsistent mesh (bad indices, degenerate tets, a node
  * with no tet, an interface pair not of one soft and one hard node).                         */
 int bpm_mesh_add(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, double demag_beta,

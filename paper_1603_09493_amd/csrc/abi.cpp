@@ -23,6 +23,7 @@ namespace bpm {
 std::string hip_err_string(hipError_t e) { return hipGetErrorString(e); }
 
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream);
+void symmetrize_device(int n, int ldS, double* S, hipStream_t stream);
 
 template <typename real>
 size_t dp5_lds_bytes(const LdsPlan&);
@@ -177,33 +178,41 @@ const char* bpm_last_error(const bpm_ctx* c) { return c ? c->err.c_str() : "null
 
 template <typename real>
 static int upload_geom(bpm_ctx* c, const MeshGroup& g, DevGeom<real>& d, Arena& A) {
+  // the CSR arrays carry kCsrPad zero entries past the last row (column 0, coefficient 0), so
+  // that a row's entries can be read in fixed-size batches without a clamp
+  const size_t nz = (size_t)g.nnz + kCsrPad;
   std::vector<real> K(g.K.begin(), g.K.end()), D(g.D.begin(), g.D.end()), DT(g.DT.begin(), g.DT.end());
+  K.resize(nz, (real)0);
+  D.resize(3 * nz, (real)0);
+  DT.resize(3 * nz, (real)0);
+  std::vector<int32_t> col(g.col.begin(), g.col.end());
+  col.resize(nz, 0);
   std::vector<real> V(g.V.begin(), g.V.end()), aif(g.aif.begin(), g.aif.end());
   HIPCHK(c, A.alloc(&d.rowptr, g.n + 1));
-  HIPCHK(c, A.alloc(&d.col, g.nnz));
-  HIPCHK(c, A.alloc(&d.colx, g.nnz));
+  HIPCHK(c, A.alloc(&d.col, nz));
+  HIPCHK(c, A.alloc(&d.colx, nz));
   HIPCHK(c, A.alloc(&d.layer, g.n));
   HIPCHK(c, A.alloc(&d.partner, g.n));
-  HIPCHK(c, A.alloc(&d.K, g.nnz));
-  HIPCHK(c, A.alloc(&d.D, 3 * (size_t)g.nnz));
-  HIPCHK(c, A.alloc(&d.DT, 3 * (size_t)g.nnz));
+  HIPCHK(c, A.alloc(&d.K, nz));
+  HIPCHK(c, A.alloc(&d.D, 3 * nz));
+  HIPCHK(c, A.alloc(&d.DT, 3 * nz));
   HIPCHK(c, A.alloc(&d.V, g.n));
   HIPCHK(c, A.alloc(&d.aif, g.n));
   HIPCHK(c, A.alloc(&d.x, g.n));
   HIPCHK(c, A.alloc(&d.y, g.n));
   HIPCHK(c, A.alloc(&d.z, g.n));
   HIPCHK(c, hipMemcpy(d.rowptr, g.rowptr.data(), sizeof(int32_t) * (g.n + 1), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(d.col, g.col.data(), sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.col, col.data(), sizeof(int32_t) * nz, hipMemcpyHostToDevice));
   {
-    std::vector<int32_t> colx(g.nnz);
+    std::vector<int32_t> colx(nz, 0);
     for (int q = 0; q < g.nnz; ++q) colx[q] = g.col[q] | (g.layer[g.col[q]] << 16);
-    HIPCHK(c, hipMemcpy(d.colx, colx.data(), sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(d.colx, colx.data(), sizeof(int32_t) * nz, hipMemcpyHostToDevice));
   }
   HIPCHK(c, hipMemcpy(d.layer, g.layer.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(d.partner, g.partner.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(d.K, K.data(), sizeof(real) * g.nnz, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(d.D, D.data(), sizeof(real) * 3 * g.nnz, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(d.DT, DT.data(), sizeof(real) * 3 * g.nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.K, K.data(), sizeof(real) * nz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.D, D.data(), sizeof(real) * 3 * nz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.DT, DT.data(), sizeof(real) * 3 * nz, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(d.V, V.data(), sizeof(real) * g.n, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(d.aif, aif.data(), sizeof(real) * g.n, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(d.x, g.x.data(), sizeof(double) * g.n, hipMemcpyHostToDevice));
@@ -261,6 +270,8 @@ int bpm_mesh_add_ex(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, doub
     rc = demag_assemble_device(*g, beta, c->own_stream, err);
     if (rc) return fail(c, rc, "bpm_mesh_add: " + err);
   }
+  symmetrize_device(n, ldS, g->dS64, c->own_stream);
+  HIPCHK(c, hipGetLastError());
   if (flags & BPM_KEEP_S32) {
     HIPCHK(c, hipMalloc(&g->dS32, sizeof(float) * (size_t)n * ldS));
     to_float_device((size_t)n * ldS, g->dS64, g->dS32, c->own_stream);
@@ -351,9 +362,9 @@ int bpm_instance_add(bpm_ctx* c, int32_t mesh_id, const bpm_material* mat, const
   }
   k.key[0] = (uint32_t)seed;
   k.key[1] = (uint32_t)(seed >> 32);
-  I.m0.resize(3 * (size_t)g.n);
-  for (int i = 0; i < g.n; ++i) {
-    double a = m0 ? m0[i] : 0.0, b = m0 ? m0[g.n + i] : 0.0, d = m0 ? m0[2 * g.n + i] : 1.0;
+  if (m0) I.m0.resize(3 * (size_t)g.n);   // no vector kept for the default state (+z everywhere)
+  for (int i = 0; m0 && i < g.n; ++i) {
+    double a = m0[i], b = m0[g.n + i], d = m0[2 * g.n + i];
     double l = std::sqrt(a * a + b * b + d * d);
     if (!(l > 0.0) || !std::isfinite(l)) {
       // a non-finite or zero initial vector is kept as is: the run reports BPM_ENONFINITE
@@ -622,7 +633,7 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     std::vector<real> m0(R * st3);
     for (int r = 0; r < R; ++r) {
       const auto& src = c->insts[by_mesh[mi][r]].m0;
-      for (size_t q = 0; q < st3; ++q) m0[r * st3 + q] = (real)src[q];
+      for (size_t q = 0; q < st3; ++q) m0[r * st3 + q] = src.empty() ? (real)(q >= 2 * (size_t)g.n) : (real)src[q];
       imap[v.inst0 + r] = make_int2(gi, r);
     }
     HIPCHK(c, hipMemcpyAsync(v.m, m0.data(), sizeof(real) * m0.size(), hipMemcpyHostToDevice, stream));
@@ -690,6 +701,8 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
   std::vector<HeunGroup<real>> hg;
   std::vector<int2> bmap;
   std::vector<int4> tmap;
+  std::vector<uint2> keys;
+  std::vector<size_t> key_off;
   int Rmax = 1;
   for (int mi = 0; mi < nm; ++mi) {
     auto& v = by_mesh[mi];
@@ -701,8 +714,9 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
     const int R = (int)v.size();
     Rmax = std::max(Rmax, R);
     HeunGroup<real> h{};
-    h.n = g.n; h.R = R; h.ldS = (g.n + 15) / 16 * 16; h.inst0 = (int)ic.size();
-    h.rowptr = d.rowptr; h.col = d.col; h.K = d.K; h.D = d.D; h.DT = d.DT;
+    key_off.push_back(keys.size());   // this group's realizations' keys start here
+    h.n = g.n; h.R = R; h.ldS = (g.n + 15) / 16 * 16; h.inst0 = (int)ic.size(); h.ldR = (R + 3) / 4 * 4;
+    h.rowptr = d.rowptr; h.col = d.col; h.colx = d.colx; h.K = d.K; h.D = d.D; h.DT = d.DT;
     h.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
     if (!h.S) return fail(c, BPM_EINVAL, "bpm_run: a mesh group does not keep S in the run precision");
     h.V = d.V; h.layer = d.layer; h.partner = d.partner; h.aif = d.aif; h.x = d.x; h.y = d.y;
@@ -712,16 +726,24 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
     HIPCHK(c, A.alloc(&h.yt, 3 * cs));
     HIPCHK(c, A.alloc(&h.k1, 3 * cs));
     HIPCHK(c, A.alloc(&h.mnext, 3 * cs));
-    HIPCHK(c, A.alloc(&h.yex, 3 * cs));
-    HIPCHK(c, A.alloc(&h.b, cs));
-    HIPCHK(c, A.alloc(&h.u, cs));
-    std::vector<real> m0(3 * cs);
+    HIPCHK(c, A.alloc(&h.b, (size_t)g.n * h.ldR));
+    HIPCHK(c, A.alloc(&h.u, (size_t)g.n * h.ldR));
+    HIPCHK(c, hipMemsetAsync(h.b, 0, sizeof(real) * g.n * h.ldR, stream));   // padding columns stay zero
+    // [3][n][R] initial state; realizations in the default state (+z) need no transposition
+    std::vector<real> m0(3 * cs, (real)0);
+    std::fill(m0.begin() + 2 * cs, m0.end(), (real)1);
+    for (int r0 = 0; r0 < R; r0 += 32)
+      for (int comp = 0; comp < 3; ++comp)
+        for (int i0 = 0; i0 < g.n; i0 += 32)
+          for (int r = r0; r < std::min(R, r0 + 32); ++r) {
+            const auto& src = c->insts[v[r]].m0;
+            if (src.empty()) continue;
+            for (int i = i0; i < std::min(g.n, i0 + 32); ++i)
+              m0[comp * cs + (size_t)i * R + r] = (real)src[(size_t)comp * g.n + i];
+          }
     c->group_inst0[mi] = (int32_t)c->inst_order.size();
     for (int r = 0; r < R; ++r) {
       const int id = v[r];
-      const auto& src = c->insts[id].m0;
-      for (int comp = 0; comp < 3; ++comp)
-        for (int i = 0; i < g.n; ++i) m0[comp * cs + (size_t)i * R + r] = (real)src[(size_t)comp * g.n + i];
       c->slot_of[id] = (int32_t)c->inst_order.size();
       c->inst_order.push_back(id);
       c->slot_group.push_back(mi);
@@ -730,46 +752,75 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
       InstConst k = c->insts[id].c;
       k.group = (int32_t)hg.size(); k.sys = (int32_t)ic.size(); k.local = r;
       ic.push_back(k);
+      keys.push_back(make_uint2(k.key[0], k.key[1]));
     }
+    // realizations that differ only in their noise key share one constant block on the device
+    h.uniform = 1;
+    for (int r = 1; r < R && h.uniform; ++r)
+      if (std::memcmp(&ic[h.inst0], &ic[h.inst0 + r], offsetof(InstConst, key)) != 0) h.uniform = 0;
     HIPCHK(c, hipMemcpyAsync(h.m, m0.data(), sizeof(real) * m0.size(), hipMemcpyHostToDevice, stream));
     c->group_m[mi] = h.m;
     const int gi = (int)hg.size();
     const long nb = ((long)g.n * R + 255) / 256;
-    for (long b = 0; b < nb; ++b) bmap.push_back(make_int2(gi, (int)b));
-    for (int m0r = 0; m0r < g.n; m0r += 64)
-      for (int n0 = 0; n0 < R; n0 += 64) tmap.push_back(make_int4(gi, m0r, n0, 0));
+    for (long b = 0; b < nb; ++b) bmap.push_back(make_int2(gi, (int)b));   // node-major: contiguous runs share neighbours
+    constexpr int T = heun_tile<real>();
+    for (int m0r = 0; m0r < g.n; m0r += T)
+      for (int n0 = 0; n0 < R; n0 += T) tmap.push_back(make_int4(gi, m0r, n0, 0));
     hg.push_back(h);
   }
   const int ng = (int)hg.size(), ninst = (int)ic.size();
   if (ng == 0) return fail(c, BPM_ESTATE, "bpm_run: no instances");
+  while (tmap.size() % 8) tmap.push_back(make_int4(-1, 0, 0, 0));   // whole rounds over the eight XCDs
+  while (bmap.size() % 8) bmap.push_back(make_int2(-1, 0));
   if (bmap.size() > 0x7fffffffu || tmap.size() > 0x7fffffffu) return fail(c, BPM_EINVAL, "bpm_run: batch too large");
   HeunGroup<real>* d_groups;
+  HeunGroup<real>* d_groups_odd;
   int2* d_bmap;
   int4* d_tmap;
   InstConst* d_ic;
   unsigned long long* d_step;
   double* d_obs;
   HIPCHK(c, A.alloc(&d_groups, ng));
+  HIPCHK(c, A.alloc(&d_groups_odd, ng));
   HIPCHK(c, A.alloc(&d_bmap, bmap.size()));
   HIPCHK(c, A.alloc(&d_tmap, tmap.size()));
   HIPCHK(c, A.alloc(&d_ic, ninst));
   HIPCHK(c, A.alloc(&d_step, 1));
   HIPCHK(c, A.alloc(&d_obs, 2 * (size_t)ninst));
   HIPCHK(c, A.alloc(&c->d_energy, ninst));
+  uint2* d_keys;
+  HIPCHK(c, A.alloc(&d_keys, keys.size()));
+  for (int gi = 0; gi < ng; ++gi) hg[gi].keys = d_keys + key_off[gi];
+  // two group tables with m and mnext swapped: steps alternate between them (no copy-back);
+  // built once every device pointer of the even table is final
+  std::vector<HeunGroup<real>> hg_odd(hg);
+  for (auto& h : hg_odd) std::swap(h.m, h.mnext);
+  for (int gi = 0; gi < ng; ++gi)
+    for (const HeunGroup<real>* h : {&hg[gi], &hg_odd[gi]})
+      if (h->keys < d_keys || h->keys + h->R > d_keys + keys.size() || !h->m || !h->mnext || h->m == h->mnext)
+        return fail(c, BPM_ESTATE, "bpm_run: inconsistent Heun group table (internal error)");
+  HIPCHK(c, hipMemcpyAsync(d_keys, keys.data(), sizeof(uint2) * keys.size(), hipMemcpyHostToDevice, stream));
   HIPCHK(c, hipMemcpyAsync(d_groups, hg.data(), sizeof(HeunGroup<real>) * ng, hipMemcpyHostToDevice, stream));
+  HIPCHK(c, hipMemcpyAsync(d_groups_odd, hg_odd.data(), sizeof(HeunGroup<real>) * ng, hipMemcpyHostToDevice, stream));
   HIPCHK(c, hipMemcpyAsync(d_bmap, bmap.data(), sizeof(int2) * bmap.size(), hipMemcpyHostToDevice, stream));
   HIPCHK(c, hipMemcpyAsync(d_tmap, tmap.data(), sizeof(int4) * tmap.size(), hipMemcpyHostToDevice, stream));
   HIPCHK(c, hipMemcpyAsync(d_ic, ic.data(), sizeof(InstConst) * ninst, hipMemcpyHostToDevice, stream));
   HIPCHK(c, hipMemsetAsync(d_step, 0, sizeof(unsigned long long), stream));
   HeunLaunch<real> L{d_groups, d_bmap, d_tmap, d_ic, (int)bmap.size(), (int)tmap.size(),
-                     HeunParams{o->dt_fixed, o->dt_fixed, o->temperature, d_step}};
+                     HeunParams{o->dt_fixed, o->dt_fixed, o->temperature, d_step}, true, true};
+  for (const auto& h : hg) {
+    L.all_uniform = L.all_uniform && h.uniform;
+    L.all_wave = L.all_wave && (h.R % 64 == 0);
+  }
   const long long nsteps = (long long)std::ceil(o->t_end / o->dt_fixed - 1e-9);
   const double h_last = o->t_end - (double)(nsteps - 1) * o->dt_fixed;
   const bool clip = nsteps > 0 && std::fabs(h_last - o->dt_fixed) > 1e-12 * o->dt_fixed;
   const long long nfull = clip ? nsteps - 1 : nsteps;
+  HeunLaunch<real> Lodd = L;
+  Lodd.groups = d_groups_odd;
   HIPCHK(c, hipEventRecord(c->ev0, stream));
-  if (nfull > 0) {
-    // one regular step captured once, replayed nfull times
+  if (nfull >= 2) {
+    // two regular steps (even table, then odd table) captured once, replayed nfull / 2 times
     hipGraph_t graph = nullptr;
     if (c->graph_exec) {
       hipGraphExecDestroy(c->graph_exec);
@@ -777,6 +828,7 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
     }
     HIPCHK(c, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     hipError_t ce = heun_step<real>(L, stream);
+    if (ce == hipSuccess) ce = heun_step<real>(Lodd, stream);
     hipError_t ee = hipStreamEndCapture(stream, &graph);
     if (ce != hipSuccess || ee != hipSuccess) {
       if (graph) hipGraphDestroy(graph);
@@ -785,15 +837,20 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
     hipError_t ie = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(c, BPM_EHIP, std::string("Heun graph instantiate: ") + hipGetErrorString(ie));
-    for (long long st = 0; st < nfull; ++st) HIPCHK(c, hipGraphLaunch(c->graph_exec, stream));
+    for (long long st = 0; st + 1 < nfull; st += 2) HIPCHK(c, hipGraphLaunch(c->graph_exec, stream));
   }
+  if (nfull % 2) HIPCHK(c, heun_step<real>(L, stream));
   if (clip) {
-    HeunLaunch<real> Ll = L;
+    HeunLaunch<real> Ll = (nfull % 2) ? Lodd : L;
     Ll.params.h = h_last;
     HIPCHK(c, heun_step<real>(Ll, stream));
   }
   HIPCHK(c, hipEventRecord(c->ev1, stream));
-  HIPCHK(c, heun_observe_launch<real>(L, ng, Rmax, d_obs, stream));
+  // the final state is in the m of the even table after an even number of steps, else of the odd one
+  const bool odd = nsteps % 2;
+  HIPCHK(c, heun_observe_launch<real>(odd ? Lodd : L, ng, Rmax, d_obs, stream));
+  for (int mi = 0, gi = 0; mi < nm; ++mi)
+    if (c->group_m[mi]) c->group_m[mi] = (odd ? hg_odd : hg)[gi++].m;
   // results in the same shapes as the DP5 path (one system per instance)
   c->run_ninst = ninst;
   c->run_nsys = ninst;

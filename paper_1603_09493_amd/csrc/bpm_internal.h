@@ -16,6 +16,21 @@
 
 namespace bpm {
 
+// Pointers loaded from memory (group views, launch parameters) are generic to the compiler; the
+// hot loops cast them to the global address space so that they compile to global_load/store,
+// which (unlike flat accesses) do not make every LDS wait also wait for outstanding HBM loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLB __attribute__((address_space(1)))
+#else
+#define GLB
+#endif
+template <typename T>
+__device__ __forceinline__ GLB T* glb(T* p) { return (GLB T*)p; }
+template <typename T>
+__device__ __forceinline__ const GLB T* glb(const T* p) { return (const GLB T*)p; }
+
+constexpr int kCsrPad = 8;   // zero CSR entries stored past the last row of every device mesh
+
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kMu0 = 4.0e-7 * kPi;          // T m / A
 constexpr double kGammaE = 1.76085963023e11;   // rad / (s T)
@@ -66,7 +81,7 @@ struct InstConst {
 struct Instance {
   int32_t mesh = 0;
   InstConst c{};
-  std::vector<double> m0;   // [3][n]
+  std::vector<double> m0;   // [3][n]; empty means every node starts along +z
   int32_t sys = -1;         // -1: own system
   bool coupled = false;
 };

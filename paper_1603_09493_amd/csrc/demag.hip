@@ -54,6 +54,20 @@ __global__ void demag_s_kernel(int n, int ldS, int e0, int e1, const int32_t* __
   S[(size_t)k * ldS + l] += acc;
 }
 
+// S <- (S + S^T) / 2, so that both triangles hold bit-identical values
+__global__ void symmetrize_kernel(int n, int ldS, double* __restrict__ S) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (l >= n || l <= k) return;
+  const double v = 0.5 * (S[(size_t)k * ldS + l] + S[(size_t)l * ldS + k]);
+  S[(size_t)k * ldS + l] = v;
+  S[(size_t)l * ldS + k] = v;
+}
+
+void symmetrize_device(int n, int ldS, double* S, hipStream_t stream) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((n + 255) / 256, n), dim3(256), 0, stream, n, ldS, S);
+}
+
 __global__ void to_float_kernel(size_t cnt, const double* __restrict__ a, float* __restrict__ b) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cnt; i += (size_t)gridDim.x * blockDim.x)
     b[i] = (float)a[i];

@@ -47,6 +47,20 @@ __device__ __forceinline__ void gauss3(uint2 key, unsigned long long step, uint3
   g[2] = r1 * cos(2.0 * kPi * u3);
 }
 
+// the same three normals with the transforms in FP32 (FP32 runs; the words are the same)
+__device__ __forceinline__ void gauss3(uint2 key, unsigned long long step, uint32_t node, float g[3]) {
+  const uint4 w = philox_10(make_uint4((uint32_t)step, (uint32_t)(step >> 32), node, 0u), key);
+  const float s = 2.3283064365386963e-10f;   // 2^-32
+  const float u0 = ((float)w.x + 0.5f) * s, u1 = ((float)w.y + 0.5f) * s;
+  const float u2 = ((float)w.z + 0.5f) * s, u3 = ((float)w.w + 0.5f) * s;
+  const float r0 = sqrtf(-2.0f * logf(u0)), r1 = sqrtf(-2.0f * logf(u2));
+  float sn, cs;
+  sincosf(6.283185307179586f * u1, &sn, &cs);
+  g[0] = r0 * cs;
+  g[1] = r0 * sn;
+  g[2] = r1 * cosf(6.283185307179586f * u3);
+}
+
 __device__ __forceinline__ void applied_field(const InstConst& c, double t, double x, double y, double& bx,
                                               double& by, double& bz) {
   double amp = c.B_peak * ((c.t_rise > 0.0) ? fmin(t / c.t_rise, 1.0) : 1.0);
@@ -62,55 +76,214 @@ __device__ __forceinline__ void applied_field(const InstConst& c, double t, doub
 }
 
 // ---------------------------------------------------------------------------------------------
-// phase A: yex = K y, b = D (Ms y) for every (node, realization)
+// Work items of phases A and C are (node i, realization r) pairs, item = i R + r, 256 per
+// workgroup.  Workgroups are spread over the XCDs in contiguous runs (workgroup w takes block
+// (w mod 8) * (blocks / 8) + w / 8 of the padded block map), so that each XCD works through a
+// contiguous range of nodes and the neighbour rows it gathers stay in its L2.  When R is a
+// multiple of 64 every wave holds one node, which the kernels then treat as wave-uniform (CSR
+// row, coefficients and per-node data through scalar loads).
 // ---------------------------------------------------------------------------------------------
+constexpr int kHG = 8;   // CSR gathers issued together
+static_assert(kHG <= kCsrPad, "a gather batch may run past the last row by kHG - 1 entries");
+
+// p[r] as base + 32-bit byte offset: with a wave-uniform base (node-uniform rows) this is one
+// scalar base and one shared VGPR offset for every gather of the row
+template <typename T>
+__device__ __forceinline__ T ld_off(const GLB T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const GLB T*>(reinterpret_cast<const GLB char*>(base) + byte_off);
+}
+
+struct HeunItem {
+  int gi, i, r;
+  bool ok;
+};
+
 template <typename real>
+__device__ __forceinline__ HeunItem heun_item(const HeunGroup<real>* __restrict__ G, const int2* __restrict__ bmap) {
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int2 bm = bmap[(bid & 7) * (nb >> 3) + (bid >> 3)];
+  HeunItem it{bm.x, 0, 0, false};
+  if (bm.x < 0) return it;
+  const int R = G[bm.x].R, n = G[bm.x].n;
+  const long item = (long)bm.y * 256 + threadIdx.x;
+  it.ok = item < (long)n * R;
+  it.i = (int)(item / R);
+  it.r = (int)(item % R);
+  return it;
+}
+
+// phase A: nodal charges b = D (Ms y) for every (node, realization)
+template <typename real, bool kU>
+__device__ __forceinline__ void heun_A_item(const HeunGroup<real>& g, const InstConst* __restrict__ inst, int i, int r,
+                                            const real* __restrict__ y) {
+  const int R = g.R;
+  const size_t cs = (size_t)g.n * R;
+  const InstConst& ic = inst[g.inst0 + (kU ? 0 : r)];
+  const real Ms0 = (real)ic.Ms[0], Ms1 = (real)ic.Ms[1];
+  const GLB real* yg = glb(y);
+  real bb = 0;
+  const uint32_t rb = (uint32_t)r * (uint32_t)sizeof(real);
+  const GLB int32_t* rp = glb(g.rowptr);
+  const GLB int32_t* cxp = glb(g.colx);
+  const GLB real* Dp = glb(g.D);
+  const int q0 = rp[i], q1 = rp[i + 1];
+  // the row's gathers are issued kHG at a time before any is used (entries past the row's end
+  // are the next rows' or the zero padding: valid columns, loaded and not summed), so that a
+  // wave keeps many loads in flight
+  for (int qb = q0; qb < q1; qb += kHG) {
+    real yx[kHG], yy[kHG], yz[kHG], d0[kHG], d1[kHG], d2[kHG];
+    int cx[kHG];
+#pragma unroll
+    for (int t = 0; t < kHG; ++t) {
+      const int q = qb + t;
+      cx[t] = cxp[q];
+      d0[t] = Dp[3 * q];
+      d1[t] = Dp[3 * q + 1];
+      d2[t] = Dp[3 * q + 2];
+      const GLB real* p = yg + (size_t)(cx[t] & 0xFFFF) * R;
+      yx[t] = ld_off(p, rb);
+      yy[t] = ld_off(p + cs, rb);
+      yz[t] = ld_off(p + 2 * cs, rb);
+    }
+#pragma unroll
+    for (int t = 0; t < kHG; ++t)
+      if (qb + t < q1) bb += ((cx[t] >> 16) ? Ms1 : Ms0) * (d0[t] * yx[t] + d1[t] * yy[t] + d2[t] * yz[t]);
+  }
+  glb(g.b)[(size_t)i * g.ldR + r] = bb;
+}
+
+// kU: every group's realizations share their constants (read once per group, uniform loads);
+// kW: every group's R is a multiple of 64 (one node per wave).  The host picks the variant for
+// the whole launch; <false, false> is correct for any batch.
+template <typename real, bool kU, bool kW>
 __global__ __launch_bounds__(256) void heun_phase_A(const HeunGroup<real>* __restrict__ G,
                                                     const int2* __restrict__ bmap, const InstConst* __restrict__ inst,
                                                     int stage) {
-  const int2 bm = bmap[blockIdx.x];
-  const HeunGroup<real> g = G[bm.x];
-  const long item = (long)bm.y * 256 + threadIdx.x;
-  const int R = g.R, n = g.n;
-  if (item >= (long)n * R) return;
-  const int i = (int)(item / R), r = (int)(item % R);
+  const HeunItem it = heun_item(G, bmap);
+  if (!it.ok) return;
+  const HeunGroup<real> g = G[it.gi];
   const real* y = stage == 0 ? g.m : g.yt;
-  const size_t cs = (size_t)n * R;
-  const InstConst& ic = inst[g.inst0 + r];
-  const real Ms0 = (real)ic.Ms[0], Ms1 = (real)ic.Ms[1];
-  real e0 = 0, e1 = 0, e2 = 0, bb = 0;
-  for (int q = g.rowptr[i]; q < g.rowptr[i + 1]; ++q) {
-    const int j = g.col[q];
-    const real yx = y[(size_t)j * R + r], yy = y[cs + (size_t)j * R + r], yz = y[2 * cs + (size_t)j * R + r];
-    const real kq = g.K[q];
-    e0 += kq * yx;
-    e1 += kq * yy;
-    e2 += kq * yz;
-    bb += (g.layer[j] ? Ms1 : Ms0) * (g.D[3 * q] * yx + g.D[3 * q + 1] * yy + g.D[3 * q + 2] * yz);
-  }
-  g.yex[(size_t)i * R + r] = e0;
-  g.yex[cs + (size_t)i * R + r] = e1;
-  g.yex[2 * cs + (size_t)i * R + r] = e2;
-  g.b[(size_t)i * R + r] = bb;
+  heun_A_item<real, kU>(g, inst, kW ? __builtin_amdgcn_readfirstlane(it.i) : it.i, it.r, y);
 }
 
 // ---------------------------------------------------------------------------------------------
-// phase B: U[N][R] = S[N][N] B[N][R] on the matrix cores; 64 x 64 output tile per workgroup,
-// each wave a 32 x 32 quarter = 2 x 2 tiles of 16 x 16; K staged through LDS 16 at a time
+// phase B: U[N][R] = S[N][N] B[N][R]
 // ---------------------------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// FP32: matrix cores.  Lane layout of v_mfma_f32_16x16x4f32 (wave64): lane l holds A[l % 16][l / 16]
-// and B[l / 16][l % 16]; the accumulator lane l holds C[4 (l / 16) + i][l % 16].
-// FP64: the same tiling with each lane owning a 4 x 4 block of its wave's 32 x 32 quarter (FMA).
+// Lane layout of v_mfma_f32_16x16x4f32 (wave64): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// the accumulator lane l holds C[4 (l / 16) + i][l % 16].
+//
+// FP32: 128 x 128 output tile per workgroup of four waves, each wave a 64 x 64 quarter = 4 x 4
+// matrix-core tiles of 16 x 16; K in slices of 16 through double-buffered LDS (global loads of
+// the next slice in flight while the current one is multiplied, one barrier per slice).  S is
+// symmetric, so A[m][k] = S[m][k] is read as S[k][m]: both operands are row segments of 128
+// values, read with 16-byte loads and stored to LDS unchanged ([k][m] and [k][n]).  The row
+// pitch of 144 values puts the four K rows of one fragment read on disjoint banks.  Tiles are
+// assigned so that the eight workgroups of a run of consecutive tiles (same mesh, same rows of
+// S) share one XCD and its L2: workgroup w runs tile (w mod 8) * (tiles / 8) + w / 8.
+constexpr int kHT = 128, kHK = 16, kHP = kHT + 16;
+
+__global__ __launch_bounds__(256) void heun_gemm_f32(const HeunGroup<float>* __restrict__ G,
+                                                     const int4* __restrict__ tmap) {
+  __shared__ float4 lds4[2 * 2 * kHK * kHP / 4];   // [buffer][operand][k][kHP]
+  float* lds = reinterpret_cast<float*>(lds4);
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int4 tm = tmap[(bid & 7) * (nb >> 3) + (bid >> 3)];
+  if (tm.x < 0) return;
+  const HeunGroup<float> g = G[tm.x];
+  const int n = g.n, R = g.R, ldS = g.ldS, ldR = g.ldR;
+  const int m0 = tm.y, n0 = tm.z;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = (wid >> 1) * 64, wc = (wid & 1) * 64;
+  // loader: rows lk and lk + 8 of the slice, columns lc .. lc + 3
+  const int lk = tid >> 5, lc = (tid & 31) * 4;
+  // every load is in bounds (columns and rows clamped) and out-of-range values are zeroed after
+  // the load, so that the loads stay unconditional global loads
+  const bool a_in = m0 + lc < ldS, b_in = n0 + lc < ldR;
+  const GLB float* Sp = glb(g.S) + (a_in ? m0 + lc : 0);
+  const GLB float* Bp = glb(g.b) + (b_in ? n0 + lc : 0);
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float* const A0 = lds;                        // buffer 0: A slice, then B slice
+  float* const A1 = lds + 2 * kHK * kHP;        // buffer 1
+  const int lo = lk * kHP + lc, hi = (lk + 8) * kHP + lc;
+#define HEUN_GLOAD(k0)                                                              \
+  do {                                                                              \
+    const int ka = (k0) + lk, kb = ka + 8;                                          \
+    const int ca = min(ka, n - 1), cb = min(kb, n - 1);                             \
+    ra0 = *reinterpret_cast<const GLB float4*>(Sp + (size_t)ca * ldS);              \
+    ra1 = *reinterpret_cast<const GLB float4*>(Sp + (size_t)cb * ldS);              \
+    rb0 = *reinterpret_cast<const GLB float4*>(Bp + (size_t)ca * ldR);              \
+    rb1 = *reinterpret_cast<const GLB float4*>(Bp + (size_t)cb * ldR);              \
+    if (!(ka < n && a_in)) ra0 = z4;                                                \
+    if (!(kb < n && a_in)) ra1 = z4;                                                \
+    if (!(ka < n && b_in)) rb0 = z4;                                                \
+    if (!(kb < n && b_in)) rb1 = z4;                                                \
+  } while (0)
+#define HEUN_LSTORE(Abuf)                                         \
+  do {                                                            \
+    *reinterpret_cast<float4*>((Abuf) + lo) = ra0;                \
+    *reinterpret_cast<float4*>((Abuf) + hi) = ra1;                \
+    *reinterpret_cast<float4*>((Abuf) + kHK * kHP + lo) = rb0;    \
+    *reinterpret_cast<float4*>((Abuf) + kHK * kHP + hi) = rb1;    \
+  } while (0)
+  float4 ra0, ra1, rb0, rb1;
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nk = (n + kHK - 1) / kHK;
+  HEUN_GLOAD(0);
+  HEUN_LSTORE(A0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) HEUN_GLOAD((kt + 1) * kHK);
+    const float* A = cur ? A1 : A0;
+    const float* B = A + kHK * kHP;
+#pragma unroll
+    for (int ks = 0; ks < kHK; ks += 4) {
+      const int kr = (ks + (lane >> 4)) * kHP + (lane & 15);
+      float af[4], bf[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = A[kr + wr + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bf[b] = B[kr + wc + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) HEUN_LSTORE(cur ? A0 : A1);
+    __syncthreads();
+  }
+#undef HEUN_GLOAD
+#undef HEUN_LSTORE
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = n0 + wc + 16 * b + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = m0 + wr + 16 * a + 4 * (lane >> 4) + i;
+        if (row < n && col < R) glb(g.u)[(size_t)row * ldR + col] = acc[a][b][i];
+      }
+    }
+}
+
+// FP64 (parity runs): 64 x 64 tiles, each lane owning a 4 x 4 block of its wave's 32 x 32 quarter
+// (FMA); the FP32 instantiation of this kernel is the 64 x 64 matrix-core variant.
 template <typename real>
 __global__ __launch_bounds__(256) void heun_phase_B(const HeunGroup<real>* __restrict__ G, const int4* __restrict__ tmap) {
   constexpr int TM = 64, TN = 64, TK = 16;
   __shared__ real As[TK][TM + 4];   // As[k][m]
   __shared__ real Bs[TK][TN + 4];   // Bs[k][n]
   const int4 tm = tmap[blockIdx.x];  // (group, m0, n0, -)
+  if (tm.x < 0) return;
   const HeunGroup<real> g = G[tm.x];
-  const int n = g.n, R = g.R, ldS = g.ldS;
+  const int n = g.n, R = g.R, ldS = g.ldS, ldR = g.ldR;
   const int m0 = tm.y, n0 = tm.z;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = (wid >> 1) * 32, wc = (wid & 1) * 32;
@@ -133,7 +306,7 @@ __global__ __launch_bounds__(256) void heun_phase_B(const HeunGroup<real>* __res
     for (int idx = tid; idx < TN * TK; idx += 256) {
       const int kk = idx / TN, nn = idx % TN;           // consecutive threads walk realizations
       const int k = k0 + kk, col = n0 + nn;
-      Bs[kk][nn] = (k < n && col < R) ? g.b[(size_t)k * R + col] : (real)0;
+      Bs[kk][nn] = (k < n && col < R) ? g.b[(size_t)k * ldR + col] : (real)0;
     }
     __syncthreads();
     if constexpr (sizeof(real) == 4) {
@@ -165,14 +338,14 @@ __global__ __launch_bounds__(256) void heun_phase_B(const HeunGroup<real>* __res
         for (int i = 0; i < 4; ++i) {
           const int row = m0 + wr + 16 * a + 4 * (lane >> 4) + i;
           const int col = n0 + wc + 16 * b + (lane & 15);
-          if (row < n && col < R) g.u[(size_t)row * R + col] = acc[a][b][i];
+          if (row < n && col < R) g.u[(size_t)row * ldR + col] = acc[a][b][i];
         }
   } else {
     const int r4 = wr + 4 * (lane >> 3), c4 = wc + 4 * (lane & 7);
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) {
         const int row = m0 + r4 + a, col = n0 + c4 + b;
-        if (row < n && col < R) g.u[(size_t)row * R + col] = (real)accd[a][b];
+        if (row < n && col < R) g.u[(size_t)row * ldR + col] = (real)accd[a][b];
       }
   }
 }
@@ -180,27 +353,58 @@ __global__ __launch_bounds__(256) void heun_phase_B(const HeunGroup<real>* __res
 // ---------------------------------------------------------------------------------------------
 // phase C: effective field + thermal field, LLG, and the Heun stage update
 // ---------------------------------------------------------------------------------------------
-template <typename real>
-__global__ __launch_bounds__(256) void heun_phase_C(const HeunGroup<real>* __restrict__ G,
-                                                    const int2* __restrict__ bmap, const InstConst* __restrict__ inst,
-                                                    const HeunParams P, int stage) {
-  const int2 bm = bmap[blockIdx.x];
-  const HeunGroup<real> g = G[bm.x];
-  const long item = (long)bm.y * 256 + threadIdx.x;
+template <typename real, bool kU>
+__device__ __forceinline__ void heun_C_item(const HeunGroup<real>& g, const InstConst* __restrict__ inst,
+                                            const HeunParams& P, int stage, int i, int r) {
   const int R = g.R, n = g.n;
-  if (item >= (long)n * R) return;
-  const int i = (int)(item / R), r = (int)(item % R);
   const size_t cs = (size_t)n * R, at = (size_t)i * R + r;
-  const InstConst& ic = inst[g.inst0 + r];
+  const InstConst& ic = inst[g.inst0 + (kU ? 0 : r)];
   const unsigned long long step = *P.step;
   const double dt = P.h;
   const double t = (double)step * P.dt + (stage == 0 ? 0.0 : dt);
   const real* y = stage == 0 ? g.m : g.yt;
   const int L = g.layer[i];
   const real Vi = g.V[i];
-  const real mx = y[at], my = y[cs + at], mz = y[2 * cs + at];
+  const GLB real* yg = glb(y);
+  const real mx = yg[at], my = yg[cs + at], mz = yg[2 * cs + at];
+  // exchange (K y) and demag (DT u) gathers over the same CSR row
+  real ex = 0, ey = 0, ez = 0, dx = 0, dy = 0, dz = 0;
+  const GLB real* ug = glb(g.u);
+  const uint32_t rb = (uint32_t)r * (uint32_t)sizeof(real);
+  const GLB int32_t* rp = glb(g.rowptr);
+  const GLB int32_t* cp = glb(g.col);
+  const GLB real* Kp = glb(g.K);
+  const GLB real* Tp = glb(g.DT);
+  const int q0 = rp[i], q1 = rp[i + 1];
+  for (int qb = q0; qb < q1; qb += kHG) {   // batched gathers as in phase A
+    real yx[kHG], yy[kHG], yz[kHG], uu[kHG], kk[kHG], t0[kHG], t1[kHG], t2[kHG];
+#pragma unroll
+    for (int t = 0; t < kHG; ++t) {
+      const int q = qb + t;
+      const int j = cp[q];
+      kk[t] = Kp[q];
+      t0[t] = Tp[3 * q];
+      t1[t] = Tp[3 * q + 1];
+      t2[t] = Tp[3 * q + 2];
+      const GLB real* p = yg + (size_t)j * R;
+      yx[t] = ld_off(p, rb);
+      yy[t] = ld_off(p + cs, rb);
+      yz[t] = ld_off(p + 2 * cs, rb);
+      uu[t] = ld_off(ug + (size_t)j * g.ldR, rb);
+    }
+#pragma unroll
+    for (int t = 0; t < kHG; ++t)
+      if (qb + t < q1) {
+        ex += kk[t] * yx[t];
+        ey += kk[t] * yy[t];
+        ez += kk[t] * yz[t];
+        dx += t0[t] * uu[t];
+        dy += t1[t] * uu[t];
+        dz += t2[t] * uu[t];
+      }
+  }
   const real cex = -(real)ic.cex[L] / Vi;
-  real Bx = cex * g.yex[at], By = cex * g.yex[cs + at], Bz = cex * g.yex[2 * cs + at];
+  real Bx = cex * ex, By = cex * ey, Bz = cex * ez;
   const real ux = (real)ic.axis[L][0], uy = (real)ic.axis[L][1], uz = (real)ic.axis[L][2];
   const real mu = (real)ic.can[L] * (mx * ux + my * uy + mz * uz);
   Bx += mu * ux; By += mu * uy; Bz += mu * uz;
@@ -208,60 +412,57 @@ __global__ __launch_bounds__(256) void heun_phase_C(const HeunGroup<real>* __res
   if (p >= 0) {
     const real ci = (real)ic.cint[L] * g.aif[i] / Vi;
     const size_t pa = (size_t)p * R + r;
-    Bx += ci * y[pa]; By += ci * y[cs + pa]; Bz += ci * y[2 * cs + pa];
-  }
-  real dx = 0, dy = 0, dz = 0;
-  for (int q = g.rowptr[i]; q < g.rowptr[i + 1]; ++q) {
-    const real uq = g.u[(size_t)g.col[q] * R + r];
-    dx += g.DT[3 * q] * uq;
-    dy += g.DT[3 * q + 1] * uq;
-    dz += g.DT[3 * q + 2] * uq;
+    Bx += ci * yg[pa]; By += ci * yg[cs + pa]; Bz += ci * yg[2 * cs + pa];
   }
   const real cd = -(real)kMu0 / Vi;
   Bx += cd * dx; By += cd * dy; Bz += cd * dz;
   double zx, zy, zz;
   applied_field(ic, t, g.x[i] + ic.off[0], g.y[i] + ic.off[1], zx, zy, zz);
+  Bx += (real)zx; By += (real)zy; Bz += (real)zz;
   // thermal field (same draw in both stages of the step)
   if (P.temperature > 0.0) {
-    double gz[3];
-    gauss3(make_uint2(ic.key[0], ic.key[1]), step, (uint32_t)i, gz);
+    real gz[3];
+    gauss3(g.keys[r], step, (uint32_t)i, gz);
     const double w = ic.Ms[L] * (double)Vi;
-    const double sig = sqrt(2.0 * ic.alpha * kBoltzmann * P.temperature / (kGammaE * w * dt));
-    zx += sig * gz[0]; zy += sig * gz[1]; zz += sig * gz[2];
+    const real sig = (real)sqrt(2.0 * ic.alpha * kBoltzmann * P.temperature / (kGammaE * w * dt));
+    Bx += sig * gz[0]; By += sig * gz[1]; Bz += sig * gz[2];
   }
-  Bx += (real)zx; By += (real)zy; Bz += (real)zz;
   const real gp = (real)ic.gp, al = (real)ic.alpha;
   const real cx = my * Bz - mz * By, cy = mz * Bx - mx * Bz, cz = mx * By - my * Bx;
   const real kx = -gp * (cx + al * (my * cz - mz * cy));
   const real ky = -gp * (cy + al * (mz * cx - mx * cz));
   const real kz = -gp * (cz + al * (mx * cy - my * cx));
   const real h = (real)dt;
+  GLB real* k1 = glb(g.k1);
   if (stage == 0) {
-    g.k1[at] = kx; g.k1[cs + at] = ky; g.k1[2 * cs + at] = kz;
-    g.yt[at] = mx + h * kx; g.yt[cs + at] = my + h * ky; g.yt[2 * cs + at] = mz + h * kz;
+    GLB real* yt = glb(g.yt);
+    k1[at] = kx; k1[cs + at] = ky; k1[2 * cs + at] = kz;
+    yt[at] = mx + h * kx; yt[cs + at] = my + h * ky; yt[2 * cs + at] = mz + h * kz;
   } else {
+    const GLB real* m = glb(g.m);
+    GLB real* mn = glb(g.mnext);
     const real hh = (real)(0.5 * dt);
-    const real ax = g.m[at] + hh * (g.k1[at] + kx);
-    const real ay = g.m[cs + at] + hh * (g.k1[cs + at] + ky);
-    const real az = g.m[2 * cs + at] + hh * (g.k1[2 * cs + at] + kz);
+    const real ax = m[at] + hh * (k1[at] + kx);
+    const real ay = m[cs + at] + hh * (k1[cs + at] + ky);
+    const real az = m[2 * cs + at] + hh * (k1[2 * cs + at] + kz);
     const real inv = (real)1 / sqrt(ax * ax + ay * ay + az * az);
-    g.mnext[at] = ax * inv; g.mnext[cs + at] = ay * inv; g.mnext[2 * cs + at] = az * inv;
+    mn[at] = ax * inv; mn[cs + at] = ay * inv; mn[2 * cs + at] = az * inv;
   }
 }
 
-// after a step: m <- mnext (swap handled by copying pointers is not graph friendly, so copy)
-template <typename real>
-__global__ void heun_commit(const HeunGroup<real>* __restrict__ G, const int2* __restrict__ bmap, HeunParams P) {
-  const int2 bm = bmap[blockIdx.x];
-  const HeunGroup<real> g = G[bm.x];
-  const long item = (long)bm.y * 256 + threadIdx.x;
-  const size_t cs = (size_t)g.n * g.R;
-  if (item < (long)cs) {
-    g.m[item] = g.mnext[item];
-    g.m[cs + item] = g.mnext[cs + item];
-    g.m[2 * cs + item] = g.mnext[2 * cs + item];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *P.step += 1ull;
+template <typename real, bool kU, bool kW>
+__global__ __launch_bounds__(256) void heun_phase_C(const HeunGroup<real>* __restrict__ G,
+                                                    const int2* __restrict__ bmap, const InstConst* __restrict__ inst,
+                                                    const HeunParams P, int stage) {
+  const HeunItem it = heun_item(G, bmap);
+  if (!it.ok) return;
+  const HeunGroup<real> g = G[it.gi];
+  heun_C_item<real, kU>(g, inst, P, stage, kW ? __builtin_amdgcn_readfirstlane(it.i) : it.i, it.r);
+}
+
+// advances the device step counter (after both stages of a step)
+__global__ void heun_tick(unsigned long long* step) {
+  if (threadIdx.x == 0) *step += 1ull;
 }
 
 // final observables per realization: volume-weighted layer means of m_z, |m| deviation
@@ -283,15 +484,27 @@ __global__ void heun_observe(const HeunGroup<real>* __restrict__ G, int ngroups,
 }
 
 // ---------------------------------------------------------------------------------------------
-template <typename real>
-hipError_t heun_step(const HeunLaunch<real>& L, hipStream_t s) {
+// one step from m into mnext (the caller alternates two group tables whose m and mnext are swapped)
+template <typename real, bool kU, bool kW>
+static void heun_step_k(const HeunLaunch<real>& L, hipStream_t s) {
   const HeunParams& P = L.params;
   for (int stage = 0; stage < 2; ++stage) {
-    hipLaunchKernelGGL(heun_phase_A<real>, dim3(L.nblk), dim3(256), 0, s, L.groups, L.bmap, L.inst, stage);
-    hipLaunchKernelGGL(heun_phase_B<real>, dim3(L.ntile), dim3(256), 0, s, L.groups, L.tmap);
-    hipLaunchKernelGGL(heun_phase_C<real>, dim3(L.nblk), dim3(256), 0, s, L.groups, L.bmap, L.inst, P, stage);
+    hipLaunchKernelGGL((heun_phase_A<real, kU, kW>), dim3(L.nblk), dim3(256), 0, s, L.groups, L.bmap, L.inst, stage);
+    if constexpr (sizeof(real) == 4)
+      hipLaunchKernelGGL(heun_gemm_f32, dim3(L.ntile), dim3(256), 0, s, L.groups, L.tmap);
+    else
+      hipLaunchKernelGGL(heun_phase_B<real>, dim3(L.ntile), dim3(256), 0, s, L.groups, L.tmap);
+    hipLaunchKernelGGL((heun_phase_C<real, kU, kW>), dim3(L.nblk), dim3(256), 0, s, L.groups, L.bmap, L.inst, P, stage);
   }
-  hipLaunchKernelGGL(heun_commit<real>, dim3(L.nblk), dim3(256), 0, s, L.groups, L.bmap, P);
+  hipLaunchKernelGGL(heun_tick, dim3(1), dim3(64), 0, s, P.step);
+}
+
+template <typename real>
+hipError_t heun_step(const HeunLaunch<real>& L, hipStream_t s) {
+  if (L.all_uniform && L.all_wave) heun_step_k<real, true, true>(L, s);
+  else if (L.all_uniform) heun_step_k<real, true, false>(L, s);
+  else if (L.all_wave) heun_step_k<real, false, true>(L, s);
+  else heun_step_k<real, false, false>(L, s);
   return hipGetLastError();
 }
 

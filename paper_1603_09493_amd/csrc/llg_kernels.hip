@@ -47,18 +47,6 @@ __constant__ double kE[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253
 template <typename real> struct Gather { static constexpr int W = 24; };
 template <> struct Gather<double> { static constexpr int W = 12; };
 
-// Pointers loaded from memory (group views, launch parameters) are generic to the compiler; the
-// hot loops cast them to the global address space so that they compile to global_load/store,
-// which (unlike flat accesses) do not make every LDS wait also wait for outstanding HBM loads.
-#if defined(__HIP_DEVICE_COMPILE__)
-#define GLB __attribute__((address_space(1)))
-#else
-#define GLB
-#endif
-template <typename T>
-__device__ __forceinline__ GLB T* glb(T* p) { return (GLB T*)p; }
-template <typename T>
-__device__ __forceinline__ const GLB T* glb(const T* p) { return (const GLB T*)p; }
 
 // ---------------------------------------------------------------------------------------------
 // small device helpers

@@ -78,6 +78,36 @@ def test_heun_clipped_last_step_and_graph_replay(ctx, oracle_mod):
     assert ctx.results([i])[0]["n_accept"] == ro[0]["n_accept"] == 41
 
 
+@pytest.mark.parametrize("R,steps,mixed", [(64, 7.0, True), (64, 7.5, False), (70, 0.6, True), (128, 2.0, False)])
+def test_heun_fp64_parity_step_parity_and_wave_layouts(ctx, oracle_mod, R, steps, mixed):
+    """Odd and even step counts (the state alternates between two buffers), a clipped final
+    step with no regular step before it, R a multiple of 64 (one node per wave) or not, and
+    realizations with shared or differing constants -- each against the oracle, every node."""
+    import dataclasses
+    from paper_1603_09493_amd import bpm
+    O = oracle_mod
+    mesh, mat, fld = I.single_island_workload(n_target=300)
+    om = O.OracleMesh(mesh)
+    S = om.demag_S()
+    dt = 5e-15
+    T = steps * dt
+    seeds = [(7 << 32) | (R << 12) | r for r in range(R)]
+    flds = [dataclasses.replace(fld, B_peak=fld.B_peak * (0.8 if (mixed and r % 3 == 1) else 1.0)) for r in range(R)]
+    _case("heun-fp64-layout", n=mesh.n, R=R, steps=steps, mixed=mixed)
+    mo, ro, _ = om.run(S, [mat] * R, flds, dict(t_end=T, integrator=O.HEUN, dt_fixed=dt, temperature=300.0),
+                       seeds=seeds)
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh, S)
+    ids = [ctx.instance_add(mid, mat, f, seed=sd) for f, sd in zip(flds, seeds)]
+    ctx.run(t_end=T, precision=64, integrator=bpm.HEUN, dt_fixed=dt, temperature=300.0)
+    ctx.sync()
+    res = ctx.results(ids)
+    for r, i in enumerate(ids):
+        assert np.abs(ctx.get_m(i, mesh.n) - mo[r]).max() <= 1e-9, r
+        assert res[r]["n_accept"] == ro[r]["n_accept"] == math.ceil(steps - 1e-9)
+        assert abs(res[r]["mz_hard"] - ro[r]["mz_hard"]) < 1e-9
+
+
 def test_free_rotational_diffusion_many_realizations(ctx):
     from paper_1603_09493_amd import bpm
     mesh = I.island_mesh(4e-9, 4e-9, 2e-9, 3e-9, 1.0e-9, seed=2)
