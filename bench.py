@@ -56,7 +56,7 @@ def surrogate_leg(n_train=1536, n_test=256, t_end=0.3e-9, n_cand=1_000_000, k=10
     from paper_1603_09493_amd import inputs as I
     from paper_1603_09493_amd import surrogate as SG
     ctx = bpm.Context(0)
-    x = I.sample_designs(n_train + n_test, seed=12, fixed_alpha_rise=False)
+    x = SG.sample(n_train + n_test, seed=12)
     lab = SG.label_designs(ctx, x, t_end=t_end, progress=log)
     solver_designs_per_s = x.shape[0] / lab.wall_s
     X = SG.scale(x).astype(np.float32)

@@ -21,8 +21,10 @@ namespace bpm {
 // which (unlike flat accesses) do not make every LDS wait also wait for outstanding HBM loads.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define GLB __attribute__((address_space(1)))
+#define LDSP __attribute__((address_space(3)))
 #else
 #define GLB
+#define LDSP
 #endif
 template <typename T>
 __device__ __forceinline__ GLB T* glb(T* p) { return (GLB T*)p; }

@@ -269,15 +269,19 @@ __host__ __device__ inline size_t lds_plan_bytes(const LdsPlan& L) {
 }
 
 // copy `cnt` 16-byte words from global memory to LDS, UN loads of a thread in flight before its
-// stores; kX: the source is exchanged data, read coherently as 8-byte halves
+// stores; kX: the source is exchanged data, read coherently as 8-byte halves.  The copy starts at
+// word rot (0 <= rot < cnt) and wraps, so that workgroups copying the same source at the same
+// time start on different memory channels.
 template <int BS, int UN, bool kX>
-__device__ __forceinline__ void copy16(uint4* __restrict__ dst, const GLB uint4* __restrict__ src, int cnt) {
+__device__ __forceinline__ void copy16(uint4* __restrict__ dst, const GLB uint4* __restrict__ src, int cnt,
+                                       int rot = 0) {
   for (int base = threadIdx.x; base < cnt; base += BS * UN) {
     uint4 v[UN];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
       const int q = base + u * BS;
-      const int qq = q < cnt ? q : cnt - 1;   // in bounds on every lane; stored only where q < cnt
+      int qq = q < cnt ? q + rot : cnt - 1;   // in bounds on every lane; stored only where q < cnt
+      if (qq >= cnt) qq -= cnt;
       if constexpr (kX) {
         const GLB unsigned long long* h = reinterpret_cast<const GLB unsigned long long*>(src + qq);
         const unsigned long long lo = xld<true>(h), hi = xld<true>(h + 1);
@@ -289,9 +293,25 @@ __device__ __forceinline__ void copy16(uint4* __restrict__ dst, const GLB uint4*
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
       const int q = base + u * BS;
-      if (q < cnt) dst[q] = v[u];
+      int qq = q + rot;
+      if (qq >= cnt) qq -= cnt;
+      if (q < cnt) dst[qq] = v[u];
     }
   }
+}
+
+// copy `cnt` 16-byte words from global memory straight into LDS (gfx950 LDS-direct loads: no
+// registers, no LDS store instructions).  Each wave fills 64 consecutive words per instruction;
+// kX: the loads carry the device-coherence bit, as the exchange loads do.  Returns after this
+// thread's loads have landed; a workgroup barrier must follow before other waves read them.
+template <int BS, bool kX>
+__device__ __forceinline__ void copy16_lds(uint4* __restrict__ dst, const GLB uint4* __restrict__ src, int cnt) {
+  for (int q0 = threadIdx.x & ~63; q0 < cnt; q0 += BS) {
+    const int q = q0 + (threadIdx.x & 63);
+    if (q < cnt)
+      __builtin_amdgcn_global_load_lds((const GLB void*)(src + q), (LDSP void*)(dst + q0), 16, 0, kX ? 16 : 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the LDS writes of this thread's loads are done
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -439,7 +459,7 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
     if (!any) continue;
     __syncthreads();
     // b rows are ldS long (zero padded), so the staging is one contiguous 16-byte copy
-    copy16<BS, 16, kX>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
+    copy16_lds<BS, kX>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
                        rn * ldS / VEC);
     __syncthreads();
     if (U <= 3) demag_rows<real, BS, kSL, kX, 3, 4>(g, i0, nr, bL, SL, part, rb, rn);

@@ -52,7 +52,8 @@ hipError_t sample_designs(uint64_t seed, long n, float* X, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 // score: predicted logit of switching where the thermal-stability proxy
 // (K_s V_s + K_h V_h) / (kB 300 K) reaches min_stability, else -inf
-// design features (indices): 0 d, 1 t_soft, 2 t_hard, 5 K_soft, 6 K_hard
+// design features (indices): 0 d, 1 t_soft, 2 t_hard, 5 K_soft, 6 K_hard; a feature with a
+// positive lower bound is a log coordinate (x = lo (hi / lo)^u), else linear (x = lo + (hi - lo) u)
 // ---------------------------------------------------------------------------------------------
 struct Range {
   double lo[12], hi[12];
@@ -62,7 +63,10 @@ __global__ void score_kernel(const float* __restrict__ X, const float* __restric
                              double min_stab, float* __restrict__ score) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     double p[12];
-    for (int f = 0; f < 12; ++f) p[f] = R.lo[f] + (R.hi[f] - R.lo[f]) * 0.5 * ((double)X[i * kMlpIn + f] + 1.0);
+    for (int f = 0; f < 12; ++f) {
+      const double u = 0.5 * ((double)X[i * kMlpIn + f] + 1.0);
+      p[f] = R.lo[f] > 0.0 ? R.lo[f] * pow(R.hi[f] / R.lo[f], u) : R.lo[f] + (R.hi[f] - R.lo[f]) * u;
+    }
     const double area = kPi * 0.25 * p[0] * p[0];
     const double stab = (p[5] * area * p[1] + p[6] * area * p[2]) / (kBoltzmann * 300.0);
     score[i] = stab >= min_stab ? Y[i * kMlpOut + 2] : -INFINITY;

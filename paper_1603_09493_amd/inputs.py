@@ -271,14 +271,40 @@ DESIGN_HI = np.array([12e-9, 8e-9, 8e-9, 1.2e6, 1.2e6, 1.5e6, 1.5e6, 10e-12,
                       math.radians(45.0), 2.0, 0.2, 0.2e-9])
 
 
-def sample_designs(n: int, seed: int = 2, fixed_alpha_rise: bool = True) -> np.ndarray:
-    """Uniform designs in the batched-island ranges; returns [n][12] float64.
+# parameters with a positive lower bound can be sampled log-uniformly (psi starts at 0: linear)
+DESIGN_LOG = DESIGN_LO > 0
+
+
+def design_of_unit(u: np.ndarray, log_prior: bool) -> np.ndarray:
+    """Designs from unit coordinates u in [0, 1]^12: lo + (hi - lo) u, or lo (hi / lo)^u for the
+    parameters in DESIGN_LOG when log_prior."""
+    u = np.asarray(u, dtype=np.float64)
+    x = DESIGN_LO + (DESIGN_HI - DESIGN_LO) * u
+    if log_prior:
+        lo, hi = DESIGN_LO[DESIGN_LOG], DESIGN_HI[DESIGN_LOG]
+        x[..., DESIGN_LOG] = lo * (hi / lo) ** u[..., DESIGN_LOG]
+    return x
+
+
+def unit_of_design(x: np.ndarray, log_prior: bool) -> np.ndarray:
+    """Inverse of design_of_unit."""
+    x = np.asarray(x, dtype=np.float64)
+    u = (x - DESIGN_LO) / (DESIGN_HI - DESIGN_LO)
+    if log_prior:
+        lo, hi = DESIGN_LO[DESIGN_LOG], DESIGN_HI[DESIGN_LOG]
+        u[..., DESIGN_LOG] = np.log(x[..., DESIGN_LOG] / lo) / np.log(hi / lo)
+    return u
+
+
+def sample_designs(n: int, seed: int = 2, fixed_alpha_rise: bool = True, log_prior: bool = False) -> np.ndarray:
+    """Designs in the batched-island ranges, uniform (or log-uniform in the parameters with a
+    positive lower bound when log_prior); returns [n][12] float64.
 
     With fixed_alpha_rise the last two entries are alpha = 0.1 and t_rise = 0.1 ns (the ranges
     of the batched-island workload do not include them)."""
     rng = np.random.default_rng(seed)
     u = rng.random((n, len(DESIGN_NAMES)))
-    x = DESIGN_LO + (DESIGN_HI - DESIGN_LO) * u
+    x = design_of_unit(u, log_prior)
     if fixed_alpha_rise:
         x[:, 10] = 0.1
         x[:, 11] = 0.1e-9

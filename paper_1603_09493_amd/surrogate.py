@@ -7,8 +7,10 @@ Here the surrogate is the MLP of the C ABI and a round proposes k designs out of
 once; the batched solver stays the judge of every pick.
 
 Design vector (12): d, t_soft, t_hard, Ms_soft, Ms_hard, K_soft, K_hard, A_int, psi, B_peak,
-alpha, t_rise -- inputs.DESIGN_LO/HI give the ranges.  Network inputs are the designs scaled to
-[-1, 1]; targets are z-scored log B_sw, z-scored log t_sw and the switched flag (masked regression
+alpha, t_rise -- inputs.DESIGN_LO/HI give the ranges.  The surrogate's designs are log-uniform in
+every parameter with a positive lower bound (psi is uniform), and the network inputs are those
+log coordinates scaled to [-1, 1], so that the screening sampler's uniform inputs are the same
+prior.  Targets are z-scored log B_sw, z-scored log t_sw and the switched flag (masked regression
 where the design did not switch).
 """
 from __future__ import annotations
@@ -26,11 +28,17 @@ KB = 1.380649e-23
 
 
 def scale(x: np.ndarray) -> np.ndarray:
-    return 2.0 * (x - I.DESIGN_LO) / (I.DESIGN_HI - I.DESIGN_LO) - 1.0
+    """Network inputs of designs x: log coordinates (linear for psi) mapped to [-1, 1]."""
+    return 2.0 * I.unit_of_design(x, log_prior=True) - 1.0
 
 
 def unscale(X: np.ndarray) -> np.ndarray:
-    return I.DESIGN_LO + (I.DESIGN_HI - I.DESIGN_LO) * 0.5 * (np.asarray(X, dtype=np.float64) + 1.0)
+    return I.design_of_unit(0.5 * (np.asarray(X, dtype=np.float64) + 1.0), log_prior=True)
+
+
+def sample(n: int, seed: int) -> np.ndarray:
+    """n designs from the surrogate's prior (log-uniform, varying alpha and the rise time)."""
+    return I.sample_designs(n, seed=seed, fixed_alpha_rise=False, log_prior=True)
 
 
 def stability(x: np.ndarray) -> np.ndarray:
@@ -171,10 +179,13 @@ def predict(net: bpm.Mlp, X: np.ndarray) -> np.ndarray:
 def bsw_predicted(sc: TargetScaler, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     """Switching field predicted for designs X (scaled) from the network outputs Y.  B_sw is the
     applied field at the island at t_sw; for the uniform ramped field of the design workload that
-    is B_peak * min(t_sw / t_rise, 1), taken here with the predicted t_sw (output 1)."""
+    is B_peak * min(t_sw / t_rise, 1).  The estimate is the geometric mean of that expression at
+    the predicted t_sw (output 1) and of the predicted B_sw (output 0): the two heads' errors are
+    partly independent."""
     x = unscale(X)
     t = np.exp(sc.t_mu + sc.t_sd * np.asarray(Y[:, 1], dtype=np.float64))
-    return x[:, 9] * np.minimum(t / x[:, 11], 1.0)
+    b_t = x[:, 9] * np.minimum(t / x[:, 11], 1.0)
+    return np.sqrt(b_t * sc.B_of(Y[:, 0]))
 
 
 def bsw_error(net: bpm.Mlp, sc: TargetScaler, X: np.ndarray, lab: Labels):

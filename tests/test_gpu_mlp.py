@@ -183,7 +183,9 @@ def test_screen_round_is_consistent(ctx, torch_mod):
     assert np.array_equal(idx.cpu().numpy(), OM.topk_reference(s, k))
     # the stability constraint removed some designs and kept the others' logits
     Xn = X.cpu().numpy().astype(np.float64)
-    p = I.DESIGN_LO + (I.DESIGN_HI - I.DESIGN_LO) * 0.5 * (Xn + 1.0)
+    u = 0.5 * (Xn + 1.0)      # log coordinates where the lower bound is positive, else linear
+    lo, hi = I.DESIGN_LO, I.DESIGN_HI
+    p = np.where(lo > 0, lo * np.power(hi / np.where(lo > 0, lo, 1.0), u), lo + (hi - lo) * u)
     area = np.pi * 0.25 * p[:, 0] ** 2
     stab = (p[:, 5] * area * p[:, 1] + p[:, 6] * area * p[:, 2]) / (1.380649e-23 * 300.0)
     ok = stab >= 40.0

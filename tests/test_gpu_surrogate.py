@@ -19,7 +19,7 @@ def test_surrogate_trains_and_screens_better_than_random():
     from paper_1603_09493_amd import surrogate as SG
     ctx = bpm.Context(0)
     n_train, n_test, t_end = 896, 128, 0.3e-9
-    x = I.sample_designs(n_train + n_test, seed=12, fixed_alpha_rise=False)
+    x = SG.sample(n_train + n_test, seed=12)
     _case("surrogate-label", n=x.shape[0])
     lab = SG.label_designs(ctx, x, t_end=t_end)
     assert np.all(lab.status == 0)
@@ -52,7 +52,7 @@ def test_surrogate_trains_and_screens_better_than_random():
     xp = SG.unscale(picks)
     assert np.all(SG.stability(xp) >= min_stab)
     rng = np.random.default_rng(5)
-    xr = I.sample_designs(4000, seed=77, fixed_alpha_rise=False)
+    xr = SG.sample(4000, seed=77)
     xr = xr[SG.stability(xr) >= min_stab][:96]
     assert xr.shape[0] == 96
     lab_p = SG.label_designs(ctx, xp, t_end=t_end)
