@@ -245,12 +245,13 @@ int bpm_sample_designs(bpm_ctx* ctx, uint64_t seed, int64_t n, float* X, void* h
 /* Indices of the k largest scores, ordered by (score descending, index ascending); NaN ranks
  * lowest.  0 < k <= min(n, 16384), n < 2^31.  idx: device int64 [k]. */
 int bpm_topk(bpm_mlp* net, const float* score, int64_t n, int64_t k, int64_t* idx, void* hip_stream);
-/* One screening round: sample n designs (as bpm_sample_designs), predict, score = predicted
- * switching logit where the thermal-stability proxy (K_s V_s + K_h V_h) / (kB 300 K) is at least
- * min_stability (else -inf), keep the top k.  lo/hi (host [12]) map X back to the physical design
- * with u = (X + 1)/2: x = lo (hi / lo)^u where lo > 0 (log coordinates), else x = lo + (hi - lo) u,
- * with the feature order d, t_soft, t_hard, Ms_soft, Ms_hard, K_soft, K_hard, A_int, psi, B_peak,
- * alpha, t_rise.  X [n][12], Y [n][3], score [n], idx [k] on device. */
+/* One screening round: sample n designs uniformly in the box [lo, hi] (host [12], finite lo < hi;
+ * the uniforms u as bpm_sample_designs, x = lo + (hi - lo) u), write their network inputs to X
+ * (log coordinates 2 log(x/lo) / log(hi/lo) - 1 where lo > 0, else 2u - 1), predict, score =
+ * predicted switching logit where the thermal-stability proxy (K_s V_s + K_h V_h) / (kB 300 K) is
+ * at least min_stability (else -inf), keep the top k.  The feature order is d, t_soft, t_hard,
+ * Ms_soft, Ms_hard, K_soft, K_hard, A_int, psi, B_peak, alpha, t_rise.  X [n][12], Y [n][3],
+ * score [n], idx [k] on device.  Errors: BPM_EINVAL for a bad size or range. */
 int bpm_screen(bpm_mlp* net, uint64_t seed, int64_t n, int64_t k, const double* lo, const double* hi,
                double min_stability, float* X, float* Y, float* score, int64_t* idx, void* hip_stream);
 

@@ -6,6 +6,7 @@ machine without it raises immediately -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import math
 import os
@@ -301,8 +302,37 @@ def _dp(x):
     return C.c_void_p(x if isinstance(x, int) else x.data_ptr())
 
 
+_SIDE = None
+
+
+@contextlib.contextmanager
+def _ts(stream):
+    """Stream argument for calls on torch tensors: the given HIP stream, else one ordered after
+    the torch work that produced the inputs and before torch's later work (and any reuse of the
+    buffers by its allocator): torch's current stream, or -- when that is the default stream,
+    whose handle 0 the library would read as its own stream -- a side stream that waits on it
+    before the call and that it waits on after the call."""
+    if stream is not None:
+        yield C.c_void_p(stream)
+        return
+    import torch
+    global _SIDE
+    cur = torch.cuda.current_stream()
+    if cur.cuda_stream:
+        yield C.c_void_p(cur.cuda_stream)
+        return
+    if _SIDE is None:
+        _SIDE = torch.cuda.Stream()
+    _SIDE.wait_stream(cur)
+    try:
+        yield C.c_void_p(_SIDE.cuda_stream)
+    finally:
+        cur.wait_stream(_SIDE)
+
+
 class Mlp:
-    """Surrogate MLP 12 -> 4 x 256 -> 3 on the GPU (bpm_mlp).  Device buffers are torch tensors."""
+    """Surrogate MLP 12 -> 4 x 256 -> 3 on the GPU (bpm_mlp).  Device buffers are torch tensors;
+    calls run on torch's current stream unless a HIP stream is given."""
 
     def __init__(self, ctx: Context, max_batch: int = 4096, theta=None):
         self.ctx, self.L = ctx, ctx.L
@@ -334,38 +364,41 @@ class Mlp:
 
     def predict(self, X, Y, n=None, stream=None):
         n = X.shape[0] if n is None else n
-        self.ctx._check(self.L.bpm_mlp_predict(self.h, _dp(X), _dp(Y), int(n), None if stream is None else C.c_void_p(stream)))
+        with _ts(stream) as st:
+            self.ctx._check(self.L.bpm_mlp_predict(self.h, _dp(X), _dp(Y), int(n), st))
 
     def grads(self, X, T, mask, batch=None):
+        import torch
         batch = X.shape[0] if batch is None else batch
         loss = C.c_float()
         g = np.empty(self.n_params, np.float32)
+        torch.cuda.current_stream().synchronize()    # the call runs on the library's own stream
         self.ctx._check(self.L.bpm_mlp_grads(self.h, _dp(X), _dp(T), _dp(mask), int(batch), C.byref(loss), _p(g)))
         return loss.value, g
 
     def train_step(self, X, T, mask, lr, batch=None, want_loss=True, stream=None):
         batch = X.shape[0] if batch is None else batch
         loss = C.c_float()
-        self.ctx._check(self.L.bpm_mlp_train_step(self.h, _dp(X), _dp(T), _dp(mask), int(batch), float(lr),
-                                                  C.byref(loss) if want_loss else None,
-                                                  None if stream is None else C.c_void_p(stream)))
+        with _ts(stream) as st:
+            self.ctx._check(self.L.bpm_mlp_train_step(self.h, _dp(X), _dp(T), _dp(mask), int(batch), float(lr),
+                                                      C.byref(loss) if want_loss else None, st))
         return loss.value if want_loss else None
 
     def topk(self, score, k, idx, n=None, stream=None):
         n = score.shape[0] if n is None else n
-        self.ctx._check(self.L.bpm_topk(self.h, _dp(score), int(n), int(k), _dp(idx),
-                                        None if stream is None else C.c_void_p(stream)))
+        with _ts(stream) as st:
+            self.ctx._check(self.L.bpm_topk(self.h, _dp(score), int(n), int(k), _dp(idx), st))
 
     def screen(self, seed, n, k, lo, hi, min_stability, X, Y, score, idx, stream=None):
         lo = np.ascontiguousarray(lo, dtype=np.float64); hi = np.ascontiguousarray(hi, dtype=np.float64)
-        self.ctx._check(self.L.bpm_screen(self.h, C.c_uint64(int(seed)), int(n), int(k), _p(lo), _p(hi),
-                                          float(min_stability), _dp(X), _dp(Y), _dp(score), _dp(idx),
-                                          None if stream is None else C.c_void_p(stream)))
+        with _ts(stream) as st:
+            self.ctx._check(self.L.bpm_screen(self.h, C.c_uint64(int(seed)), int(n), int(k), _p(lo), _p(hi),
+                                              float(min_stability), _dp(X), _dp(Y), _dp(score), _dp(idx), st))
 
 
 def sample_designs(ctx: Context, seed, n, X, stream=None):
-    ctx._check(ctx.L.bpm_sample_designs(ctx.h, C.c_uint64(int(seed)), int(n), _dp(X),
-                                        None if stream is None else C.c_void_p(stream)))
+    with _ts(stream) as st:
+        ctx._check(ctx.L.bpm_sample_designs(ctx.h, C.c_uint64(int(seed)), int(n), _dp(X), st))
 
 
 def nan_to_none(x):

@@ -1264,9 +1264,13 @@ int bpm_screen(bpm_mlp* M, uint64_t seed, int64_t n, int64_t k, const double* lo
   bpm_ctx* c = M->ctx;
   if (!lo || !hi || !X || !Y || !score || !idx || n <= 0 || n > 0x7fffffffLL || k <= 0 || k > n || k > kTopkMax)
     return fail(c, BPM_EINVAL, "bpm_screen: bad argument");
+  for (int f = 0; f < 12; ++f)
+    if (!(hi[f] > lo[f]) || !std::isfinite(lo[f]) || !std::isfinite(hi[f]))
+      return fail(c, BPM_EINVAL, "bpm_screen: every range needs finite lo < hi");
   hipSetDevice(c->device);
   hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
   HIPCHK(c, sample_designs(seed, (long)n, X, s));
+  HIPCHK(c, design_features(X, (long)n, lo, hi, s));
   HIPCHK(c, mlp_predict(M->net, X, Y, (long)n, s));
   HIPCHK(c, screen_score(X, Y, (long)n, lo, hi, min_stability, score, s));
   HIPCHK(c, topk_select(score, (long)n, (long)k, idx, M->sc, s));

@@ -51,6 +51,7 @@ struct ScreenScratch {
 };
 constexpr long kTopkMax = 16384;
 hipError_t sample_designs(uint64_t seed, long n, float* X, hipStream_t s);
+hipError_t design_features(float* X, long n, const double* lo, const double* hi, hipStream_t s);
 hipError_t topk_select(const float* score, long n, long k, int64_t* idx, ScreenScratch& sc, hipStream_t s);
 hipError_t screen_score(const float* X, const float* Y, long n, const double* lo, const double* hi, double min_stability,
                         float* score, hipStream_t s);

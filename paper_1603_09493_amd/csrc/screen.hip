@@ -50,14 +50,41 @@ hipError_t sample_designs(uint64_t seed, long n, float* X, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// network inputs of sampled designs, in place: a sample X = 2u - 1 stands for the design
+// x = lo + (hi - lo) u (uniform prior); features with lo > 0 become log coordinates
+// 2 log(x / lo) / log(hi / lo) - 1, the others stay 2u - 1
+// ---------------------------------------------------------------------------------------------
+struct Range {
+  double lo[12], hi[12];
+};
+
+__global__ void features_kernel(float* __restrict__ X, long n, Range R) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    for (int f = 0; f < 12; ++f) {
+      if (!(R.lo[f] > 0.0)) continue;
+      const double u = 0.5 * ((double)X[i * kMlpIn + f] + 1.0);
+      const double x = R.lo[f] + (R.hi[f] - R.lo[f]) * u;
+      X[i * kMlpIn + f] = (float)(2.0 * log(x / R.lo[f]) / log(R.hi[f] / R.lo[f]) - 1.0);
+    }
+  }
+}
+
+hipError_t design_features(float* X, long n, const double* lo, const double* hi, hipStream_t s) {
+  Range R;
+  for (int f = 0; f < 12; ++f) {
+    R.lo[f] = lo[f];
+    R.hi[f] = hi[f];
+  }
+  hipLaunchKernelGGL(features_kernel, dim3(2048), dim3(256), 0, s, X, n, R);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // score: predicted logit of switching where the thermal-stability proxy
 // (K_s V_s + K_h V_h) / (kB 300 K) reaches min_stability, else -inf
 // design features (indices): 0 d, 1 t_soft, 2 t_hard, 5 K_soft, 6 K_hard; a feature with a
 // positive lower bound is a log coordinate (x = lo (hi / lo)^u), else linear (x = lo + (hi - lo) u)
 // ---------------------------------------------------------------------------------------------
-struct Range {
-  double lo[12], hi[12];
-};
 
 __global__ void score_kernel(const float* __restrict__ X, const float* __restrict__ Y, long n, Range R,
                              double min_stab, float* __restrict__ score) {

@@ -7,11 +7,10 @@ Here the surrogate is the MLP of the C ABI and a round proposes k designs out of
 once; the batched solver stays the judge of every pick.
 
 Design vector (12): d, t_soft, t_hard, Ms_soft, Ms_hard, K_soft, K_hard, A_int, psi, B_peak,
-alpha, t_rise -- inputs.DESIGN_LO/HI give the ranges.  The surrogate's designs are log-uniform in
-every parameter with a positive lower bound (psi is uniform), and the network inputs are those
-log coordinates scaled to [-1, 1], so that the screening sampler's uniform inputs are the same
-prior.  Targets are z-scored log B_sw, z-scored log t_sw and the switched flag (masked regression
-where the design did not switch).
+alpha, t_rise -- inputs.DESIGN_LO/HI give the ranges.  Designs are uniform in the box; the
+network inputs are log coordinates (psi linear) scaled to [-1, 1] -- the screening round maps its
+uniform samples the same way on the GPU.  Targets are z-scored log B_sw, z-scored log t_sw and the
+switched flag (masked regression where the design did not switch).
 """
 from __future__ import annotations
 
@@ -37,8 +36,8 @@ def unscale(X: np.ndarray) -> np.ndarray:
 
 
 def sample(n: int, seed: int) -> np.ndarray:
-    """n designs from the surrogate's prior (log-uniform, varying alpha and the rise time)."""
-    return I.sample_designs(n, seed=seed, fixed_alpha_rise=False, log_prior=True)
+    """n designs from the surrogate's prior (uniform in the box, alpha and the rise time varying)."""
+    return I.sample_designs(n, seed=seed, fixed_alpha_rise=False)
 
 
 def stability(x: np.ndarray) -> np.ndarray:
@@ -59,7 +58,7 @@ class Labels:
 
 
 def label_designs(ctx: bpm.Context, x: np.ndarray, t_end: float = 0.5e-9, precision: int = 32,
-                  mesh_seed: int = 0, clear: bool = True, chunk: int = 96, work: float = 2.5e8,
+                  mesh_seed: int = 0, clear: bool = True, chunk: int = 512, work: float = 1.0e9,
                   progress=None) -> Labels:
     """Runs every design (rows of x) as one island, in batched launches of designs of similar size,
     each launch holding at most `chunk` designs and at most `work` summed N^2 (so that the launcher

@@ -186,6 +186,15 @@ def test_screen_round_is_consistent(ctx, torch_mod):
     u = 0.5 * (Xn + 1.0)      # log coordinates where the lower bound is positive, else linear
     lo, hi = I.DESIGN_LO, I.DESIGN_HI
     p = np.where(lo > 0, lo * np.power(hi / np.where(lo > 0, lo, 1.0), u), lo + (hi - lo) * u)
+    # the inputs are the log coordinates of designs drawn uniformly in the box: the sampler's
+    # uniforms (same seed), mapped on the host
+    U = torch.empty_like(X)
+    bpm.sample_designs(ctx, 11, n, U)
+    u0 = 0.5 * (U.cpu().numpy().astype(np.float64) + 1.0)
+    x0 = lo + (hi - lo) * u0
+    f0 = np.where(lo > 0, 2 * np.log(x0 / np.where(lo > 0, lo, 1.0)) / np.log(hi / np.where(lo > 0, lo, 1.0)) - 1,
+                  2 * u0 - 1)
+    assert np.abs(Xn - f0).max() < 2e-6
     area = np.pi * 0.25 * p[:, 0] ** 2
     stab = (p[:, 5] * area * p[:, 1] + p[:, 6] * area * p[:, 2]) / (1.380649e-23 * 300.0)
     ok = stab >= 40.0

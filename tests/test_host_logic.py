@@ -16,16 +16,17 @@ def test_design_scaling_round_trip_and_bounds():
     np.testing.assert_allclose(SG.scale(I.DESIGN_HI[None]), 1.0, atol=1e-12)
 
 
-def test_log_prior_is_uniform_in_log_coordinates():
-    """Parameters with a positive lower bound are log-uniform (their geometric midpoint is the
-    median), psi is uniform (its arithmetic midpoint is the median)."""
+def test_prior_is_uniform_and_inputs_are_log_coordinates():
+    """The surrogate's designs are uniform in the box (arithmetic midpoints are the medians);
+    the network input of a parameter with a positive lower bound is its log coordinate (the
+    geometric midpoint maps to 0), psi's is linear."""
     x = SG.sample(200_000, seed=5)
     med = np.median(x, axis=0)
-    geo = np.sqrt(I.DESIGN_LO * I.DESIGN_HI)
     mid = 0.5 * (I.DESIGN_LO + I.DESIGN_HI)
     for f in range(12):
-        ref = geo[f] if I.DESIGN_LOG[f] else mid[f]
-        assert abs(med[f] / ref - 1) < 0.01, (I.DESIGN_NAMES[f], med[f], ref)
+        assert abs(med[f] / mid[f] - 1) < 0.01, (I.DESIGN_NAMES[f], med[f], mid[f])
+    geo = np.where(I.DESIGN_LOG, np.sqrt(np.abs(I.DESIGN_LO * I.DESIGN_HI)), mid)
+    np.testing.assert_allclose(SG.scale(geo[None])[0], 0.0, atol=1e-12)
     assert not I.DESIGN_LOG[I.DESIGN_NAMES.index("psi")]
 
 
