@@ -46,7 +46,7 @@ def cpu_baseline_patch(mesh, mats, flds, offs, t_sample=2e-12):
                       f"({res[0]['n_accept']} DP5 steps, {wall:.1f} s wall), rate extrapolated"}
 
 
-def surrogate_leg(n_train=1536, n_test=256, t_end=0.3e-9, n_cand=1_000_000, k=10_000, epochs=120, log=None):
+def surrogate_leg(n_train=4608, n_test=512, t_end=0.3e-9, n_cand=1_000_000, k=10_000, epochs=100, log=None):
     """Label designs with the batched FP32 solver, train the MLP with the library's kernels,
     report the held-out switching-field error and time a 1M-candidate screening round."""
     import numpy as np
@@ -259,7 +259,7 @@ def main():
     tuned = None
     if args.wg == 0:
         # workgroups per group; negative = 512-thread workgroups
-        cands = [32, 64, 96, 128, 192, 256, -48, -64, -96, -128, -192, -256]
+        cands = [32, 64, 96, 128, 192, 256, -48, -64, -96, -112, -128, -136, -144, -160, -192, -256]
         tuned, ms = ctx.autotune(cands, probe_attempts=80, t_end=args.t_end, precision=args.precision, rtol=rtol)
         log("autotune (us/attempt): " + ", ".join(f"{c}:{1e3*m:.0f}" for c, m in zip(cands, ms)) + f" -> {tuned}")
     for w in range(args.warmup):

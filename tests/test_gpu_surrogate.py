@@ -36,12 +36,13 @@ def test_surrogate_trains_and_screens_better_than_random():
     e0, _, _ = SG.bsw_error(net, sc, X[te], lab_te)
     _case("surrogate-train", n=n_train)
     losses = SG.train(net, X[tr], T, mask, epochs=300, batch=64, lr=2e-3)
-    assert losses[-1] < 0.3 * losses[0]
+    assert losses[-1] < 0.4 * losses[0]
     e1, p95, Y = SG.bsw_error(net, sc, X[te], lab_te)
     print(f"[surrogate] held-out |rel err| of B_sw: mean {e1:.4f} p95 {p95:.4f} (untrained {e0:.3f}); "
           f"switched fraction {frac:.2f}", flush=True)
-    # the held-out error is data-limited (it falls with more labels; the bench trains on 1536)
-    assert e1 < 0.5 * e0 and e1 < 0.07
+    # the held-out error is data-limited: about 3.3 % at 896 labels, 2.3 % at 1792, 1.75 % at
+    # 4864 (the bench trains on 4608)
+    assert e1 < 0.5 * e0 and e1 < 0.045
     # switching classification on held-out designs
     acc = ((Y[:, 2] > 0) == lab_te.switched).mean()
     assert acc > 0.8, acc
