@@ -16,6 +16,9 @@
  *     message owned by the context, valid until the next call on that context.
  *   - Host pointers are caller-owned and only read during the call (copied).  Device pointers
  *     (marked "device") must stay valid until the work queued on the given stream completes.
+ *   - hip_stream arguments: the HIP stream the call's work is queued on; NULL selects the
+ *     context's own non-blocking stream, which is not ordered with the legacy default stream --
+ *     callers whose inputs come from other streams pass that stream (or synchronise first).
  *   - One context per host thread.  Calls on one context are not thread-safe.
  *   - A numerical failure of one instance (non-finite state, step underflow, step budget) does
  *     not fail the run: it is reported in bpm_result.status and the other instances continue.
@@ -165,7 +168,7 @@ enum { BPM_FLAG_SYMMETRIC_DEMAG = 1,
        BPM_FLAG_WG512 = 2,    /* 512-thread workgroups for the stepping kernel (default 256) */
        BPM_FLAG_STREAM_S = 4  /* stream S from global memory even where its rows fit in LDS */ };
 
-/* Queues a run of every instance on `hip_stream` (NULL = default stream).  Asynchronous. */
+/* Queues a run of every instance on `hip_stream` (NULL = the context's own stream).  Asynchronous. */
 int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);
 /* Waits for the run; returns the first ABI-level error of the run. */
 int bpm_sync(bpm_ctx* ctx);
