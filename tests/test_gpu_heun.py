@@ -108,6 +108,35 @@ def test_heun_fp64_parity_step_parity_and_wave_layouts(ctx, oracle_mod, R, steps
         assert abs(res[r]["mz_hard"] - ro[r]["mz_hard"]) < 1e-9
 
 
+@pytest.mark.parametrize("R", [200, 256])
+def test_heun_fp32_matrix_core_path_against_oracle(ctx, oracle_mod, R):
+    """FP32 runs use the 128 x 128 matrix-core demag product (ragged in both dimensions here:
+    N = 324 rows in tiles of 128, R = 200 columns = 128 + 72; R = 256 also takes the wave-uniform
+    field kernels) and FP32 noise transforms: every node of every realization against the FP64
+    oracle with the same Philox noise.  Bar: 2e-4 after 10 steps at 300 K (FP32 rounding; a wrong
+    tile or lane mapping of the product gives errors of order 1e-2 and more)."""
+    from paper_1603_09493_amd import bpm
+    O = oracle_mod
+    mesh, mat, fld = I.single_island_workload(n_target=300)
+    om = O.OracleMesh(mesh)
+    S = om.demag_S()
+    seeds = [(11 << 32) | (R << 12) | r for r in range(R)]
+    T, dt, Temp = 10 * 5e-15, 5e-15, 300.0
+    _case("heun-fp32-mfma", n=mesh.n, R=R, steps=10)
+    mo, ro, _ = om.run(S, [mat] * R, [fld] * R, dict(t_end=T, integrator=O.HEUN, dt_fixed=dt, temperature=Temp),
+                       seeds=seeds)
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh, S, keep=3)
+    ids = [ctx.instance_add(mid, mat, fld, seed=sd) for sd in seeds]
+    ctx.run(t_end=T, precision=32, integrator=bpm.HEUN, dt_fixed=dt, temperature=Temp)
+    ctx.sync()
+    worst = max(float(np.abs(ctx.get_m(i, mesh.n) - mo[r]).max()) for r, i in enumerate(ids))
+    print(f"[heun-fp32] R={R}: max |dm| = {worst:.2e}", flush=True)
+    assert worst <= 2e-4
+    # the noise acted: realizations differ far beyond the bar
+    assert np.abs(mo[0] - mo[1]).max() > 1e-3
+
+
 def test_free_rotational_diffusion_many_realizations(ctx):
     from paper_1603_09493_amd import bpm
     mesh = I.island_mesh(4e-9, 4e-9, 2e-9, 3e-9, 1.0e-9, seed=2)
