@@ -165,8 +165,10 @@ typedef struct {
  * several workgroups keep each workgroup's rows of S in LDS for the whole launch when they fit
  * (the demag product then reads no S from HBM); BPM_FLAG_STREAM_S turns that off. */
 enum { BPM_FLAG_SYMMETRIC_DEMAG = 1,
-       BPM_FLAG_WG512 = 2,    /* 512-thread workgroups for the stepping kernel (default 256) */
-       BPM_FLAG_STREAM_S = 4  /* stream S from global memory even where its rows fit in LDS */ };
+       BPM_FLAG_WG512 = 2,    /* 512-thread workgroups for the stepping kernel (default: 512 for
+                                 runs of several mesh groups, else 256 unless tuned) */
+       BPM_FLAG_STREAM_S = 4, /* stream S from global memory even where its rows fit in LDS */
+       BPM_FLAG_WG256 = 8     /* 256-thread workgroups whatever the default */ };
 
 /* Queues a run of every instance on `hip_stream` (NULL = the context's own stream).  Asynchronous. */
 int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);

