@@ -46,7 +46,7 @@ def cpu_baseline_patch(mesh, mats, flds, offs, t_sample=2e-12):
                       f"({res[0]['n_accept']} DP5 steps, {wall:.1f} s wall), rate extrapolated"}
 
 
-def surrogate_leg(n_train=4608, n_test=512, t_end=0.3e-9, n_cand=1_000_000, k=10_000, epochs=100, log=None):
+def surrogate_leg(n_train=8192, n_test=512, t_end=0.3e-9, n_cand=1_000_000, k=10_000, epochs=100, log=None):
     """Label designs with the batched FP32 solver, train the MLP with the library's kernels,
     report the held-out switching-field error and time a 1M-candidate screening round."""
     import numpy as np
