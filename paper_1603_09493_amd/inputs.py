@@ -194,8 +194,31 @@ def island_mesh(a: float, b: float, t_soft: float, t_hard: float, h: float, seed
     neg = det < 0
     tet[neg, 2], tet[neg, 3] = tet[neg, 3].copy(), tet[neg, 2].copy()
     iface = np.stack([nh * n2 + np.arange(n2), (nh - 1) * n2 + np.arange(n2)], axis=1)
+    # Renumber the nodes by reverse Cuthill-McKee over the graph of tet edges and interface pairs
+    # (the level-major numbering above puts every row's neighbours a whole level apart): nodes
+    # that share a tet, or an interface pair, get nearby indices.  Relabelling changes nothing
+    # physical.
+    perm = _rcm_order(n, tet, iface)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    xyz = xyz[:, perm]
+    layer = layer[perm]
+    tet = inv[tet]
+    iface = inv[iface]
     return Mesh(xyz=np.ascontiguousarray(xyz), tet=np.ascontiguousarray(tet.astype(np.int32)),
                 layer=layer, iface=np.ascontiguousarray(iface.astype(np.int32)), n2d=n2)
+
+
+def _rcm_order(n: int, tet: np.ndarray, iface: np.ndarray) -> np.ndarray:
+    """Reverse Cuthill-McKee order of the node graph (edges of the tets and interface pairs)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    pairs = [tet[:, [a, b]] for a in range(4) for b in range(a + 1, 4)] + [iface]
+    e = np.concatenate(pairs, axis=0)
+    r = np.concatenate([e[:, 0], e[:, 1]])
+    c = np.concatenate([e[:, 1], e[:, 0]])
+    g = coo_matrix((np.ones(r.size, dtype=np.int8), (r, c)), shape=(n, n)).tocsr()
+    return np.asarray(reverse_cuthill_mckee(g, symmetric_mode=True), dtype=np.int64)
 
 
 def island_mesh_target(a: float, b: float, t_soft: float, t_hard: float, n_target: int,
