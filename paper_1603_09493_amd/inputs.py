@@ -151,7 +151,7 @@ def _levels(t: float, hz: float) -> np.ndarray:
 
 
 def island_mesh(a: float, b: float, t_soft: float, t_hard: float, h: float, seed: int = 0,
-                jitter: float = 0.15) -> Mesh:
+                jitter: float = 0.15, renumber: bool = True) -> Mesh:
     """Extruded ECC island: hard layer z in [0, t_hard], soft layer z in [t_hard, t_hard+t_soft].
 
     a, b are the semi-axes (a = b for a cylinder); h is the target edge length.
@@ -198,7 +198,7 @@ def island_mesh(a: float, b: float, t_soft: float, t_hard: float, h: float, seed
     # (the level-major numbering above puts every row's neighbours a whole level apart): nodes
     # that share a tet, or an interface pair, get nearby indices.  Relabelling changes nothing
     # physical.
-    perm = _rcm_order(n, tet, iface)
+    perm = _rcm_order(n, tet, iface) if renumber else np.arange(n)
     inv = np.empty(n, dtype=np.int64)
     inv[perm] = np.arange(n)
     xyz = xyz[:, perm]

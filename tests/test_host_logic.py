@@ -38,3 +38,37 @@ def test_linear_prior_unchanged_for_the_batched_workload():
     ref[:, 10] = 0.1
     ref[:, 11] = 0.1e-9
     np.testing.assert_array_equal(x, ref)
+
+
+def _spread(mesh):
+    out = np.zeros(mesh.n, int)
+    for e in mesh.tet:
+        out[e] = np.maximum(out[e], np.abs(e[:, None] - e[None, :]).max(axis=1))
+    return out
+
+
+def test_mesher_renumbering_is_a_relabelling_with_smaller_spread():
+    """The reverse Cuthill-McKee renumbering is a relabelling of the level-major mesh (same node
+    coordinates and layers, same tets and interface pairs up to the permutation, still positively
+    oriented) and shrinks the index spread of every node's neighbours."""
+    args = (9e-9, 2.25e-9, 3e-9, 7e-9, 1.0e-9)
+    m0 = I.island_mesh(*args, seed=1, renumber=False)
+    m1 = I.island_mesh(*args, seed=1)
+    n = m0.n
+    assert m1.n == n and m1.tet.shape == m0.tet.shape
+    # the permutation: match nodes by (coordinates, layer) -- interface copies differ in layer
+    def key(m):
+        return [tuple(np.round(m.xyz[:, i] * 1e12).astype(np.int64)) + (int(m.layer[i]),) for i in range(m.n)]
+    k0, k1 = key(m0), key(m1)
+    pos1 = {k: i for i, k in enumerate(k1)}
+    assert len(pos1) == n
+    perm = np.array([pos1[k] for k in k0])          # old index -> new index
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    np.testing.assert_array_equal(perm[m0.tet], m1.tet)
+    np.testing.assert_array_equal(perm[m0.iface], m1.iface)
+    P = m1.xyz.T
+    t = m1.tet
+    det = np.einsum("ij,ij->i", P[t[:, 1]] - P[t[:, 0]], np.cross(P[t[:, 2]] - P[t[:, 0]], P[t[:, 3]] - P[t[:, 0]]))
+    assert np.all(det > 0)
+    s0, s1 = _spread(m0), _spread(m1)
+    assert s1.max() < 0.8 * s0.max() and s1.mean() < 0.8 * s0.mean(), (s0.max(), s1.max(), s0.mean(), s1.mean())
