@@ -168,7 +168,22 @@ enum { BPM_FLAG_SYMMETRIC_DEMAG = 1,
        BPM_FLAG_WG512 = 2,    /* 512-thread workgroups for the stepping kernel (default: 512 for
                                  runs of several mesh groups, else 256 unless tuned) */
        BPM_FLAG_STREAM_S = 4, /* stream S from global memory even where its rows fit in LDS */
-       BPM_FLAG_WG256 = 8     /* 256-thread workgroups whatever the default */ };
+       BPM_FLAG_WG256 = 8,    /* 256-thread workgroups whatever the default */
+       BPM_FLAG_CONTINUE = 16 /* continue the previous DP5 run (see below) */ };
+
+/* BPM_FLAG_CONTINUE: instead of starting from m0 at t = 0, the run continues the last
+ * BPM_DP45 / BPM_DP5_FIXED run of this context up to the new t_end (>= the previous end): the
+ * magnetisation and first-stage slope of the last accepted step, the time, next step size and
+ * growth cap of the controller, the step counters (max_steps counts from the first run), the
+ * switching-time crossing state and the trajectory buffer carry over.  The instance set must not
+ * have changed since that run (BPM_ESTATE otherwise); integrator and precision must match and
+ * the launch shape and other flags of that run are kept; rtol, atol, dt_min, max_steps and
+ * save_every are taken from this call.  A fixed-step run continues only with the same dt_fixed
+ * and a previous end on its time grid (BPM_EINVAL).  The last step before each end is shortened
+ * to land on it, so a run split at intermediate ends takes that step sequence; the adaptive
+ * controller then resumes with the step it had planned before the shortening when that is longer.
+ * Fixed-step runs split on their grid take the same steps as one run (the split step ends at the
+ * requested end time, which can differ from the grid time by rounding). */
 
 /* Queues a run of every instance on `hip_stream` (NULL = the context's own stream).  Asynchronous. */
 int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);

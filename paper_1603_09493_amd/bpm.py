@@ -23,6 +23,7 @@ FLAG_SYMMETRIC_DEMAG = 1
 FLAG_WG512 = 2
 FLAG_STREAM_S = 4
 FLAG_WG256 = 8
+FLAG_CONTINUE = 16
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
 
@@ -211,10 +212,13 @@ class Context:
         self._check(self.L.bpm_mesh_get_S(self.h, mid, _p(S)))
         return S
 
-    def mesh_get_assembly(self, mid):
+    def mesh_get_assembly(self, mid, pattern_only=False):
+        """Host-assembled quantities of a group (dict), or only the pattern size nnz."""
         n = self.mesh_n[mid]
         nnz = C.c_int32()
         self._check(self.L.bpm_mesh_get_assembly(self.h, mid, C.byref(nnz), None, None, None, None, None, None))
+        if pattern_only:
+            return nnz.value
         V = np.empty(n); rp = np.empty(n + 1, np.int32); col = np.empty(nnz.value, np.int32)
         K = np.empty(nnz.value); D = np.empty((nnz.value, 3)); aif = np.empty(n)
         self._check(self.L.bpm_mesh_get_assembly(self.h, mid, C.byref(nnz), _p(V), _p(rp), _p(col), _p(K), _p(D),

@@ -108,6 +108,18 @@ struct bpm_ctx {
   double* heun_obs = nullptr;
   long long heun_nsteps = 0;
   double heun_dt = 0.0, heun_t_end = 0.0;
+  // launch of the last stepping run, kept so that a run with BPM_FLAG_CONTINUE can resume it
+  bool run_resumable = false;
+  int64_t inst_version = 0, run_version = -1;   // bumped by every change of the instance set
+  int run_integrator = -1, run_flags = 0;
+  bool run_fixed = false, run_coop = false;
+  double run_t_end = 0.0, run_dt_fixed = 0.0;
+  RunParams run_P{};
+  void* run_d_groups = nullptr;
+  int2* run_d_imap = nullptr;
+  int run_nmax = 0, run_ng = 0;
+  double *run_d_err = nullptr, *run_d_obs = nullptr, *run_d_mom = nullptr;
+  unsigned long long* run_d_bar = nullptr;
   // autotuned workgroups per mesh group, keyed by (log2 bucket of N, instances, precision)
   std::map<std::tuple<int, int, int>, int> tune;
   std::string tune_path;
@@ -377,6 +389,7 @@ int bpm_instance_add(bpm_ctx* c, int32_t mesh_id, const bpm_material* mat, const
   *inst_id = (int32_t)c->insts.size();
   c->insts.push_back(std::move(I));
   c->have_results = false;
+  c->inst_version++;
   return BPM_OK;
 }
 
@@ -402,6 +415,7 @@ int bpm_couple_dipoles(bpm_ctx* c, int32_t n, const int32_t* ids) {
     c->insts[ids[i]].sys = ids[0];
   }
   c->have_results = false;
+  c->inst_version++;
   return BPM_OK;
 }
 
@@ -410,6 +424,7 @@ int bpm_clear_instances(bpm_ctx* c) {
   if (c->run_pending) return fail(c, BPM_ESTATE, "bpm_clear_instances: a run is pending; call bpm_sync first");
   c->insts.clear();
   c->have_results = false;
+  c->inst_version++;
   return BPM_OK;
 }
 
@@ -674,7 +689,8 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   P.t_end = o->t_end; P.dt0 = o->dt0; P.dt_fixed = o->dt_fixed; P.rtol = o->rtol; P.atol = o->atol;
   P.dt_min = o->dt_min; P.temperature = o->temperature; P.max_steps = o->max_steps;
   P.save_every = o->save_every; P.traj_cap = tcap;
-  P.flags = o->flags;
+  P.flags = o->flags & ~BPM_FLAG_CONTINUE;
+  P.resume = 0;
   P.inst = d_ic; P.sys = d_sys; P.sys_out = c->d_sys_out; P.inst_out = c->d_inst_out; P.traj = c->d_traj;
   P.err_acc = d_err; P.obs_acc = d_obs; P.mom_acc = d_mom; P.wg_map = d_map;
 
@@ -692,6 +708,60 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   c->run_nsys = nsys;
   c->run_traj_cap = tcap;
   c->run_precision = sizeof(real) == 8 ? 64 : 32;
+  c->run_stream = stream;
+  c->run_pending = true;
+  c->have_results = false;
+  c->run_resumable = true;
+  c->run_version = c->inst_version;
+  c->run_integrator = o->integrator;
+  c->run_flags = o->flags & ~BPM_FLAG_CONTINUE;
+  c->run_fixed = fixed;
+  c->run_coop = coop;
+  c->run_t_end = o->t_end;
+  c->run_dt_fixed = o->dt_fixed;
+  c->run_P = P;
+  c->run_d_groups = d_groups;
+  c->run_d_imap = d_imap;
+  c->run_nmax = nmax;
+  c->run_ng = ng;
+  c->run_d_err = d_err;
+  c->run_d_obs = d_obs;
+  c->run_d_mom = d_mom;
+  c->run_d_bar = d_bar;
+  return BPM_OK;
+}
+
+// Continues the last stepping run up to the new t_end: same instances, buffers and launch shape;
+// the kernel starts from the state, controller and crossing data the previous launch stored.
+template <typename real>
+static int resume_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
+  RunParams P = c->run_P;
+  P.t_end = o->t_end;
+  P.rtol = o->rtol;
+  P.atol = o->atol;
+  P.dt_min = o->dt_min;
+  P.max_steps = o->max_steps;
+  P.save_every = o->save_every;
+  P.resume = 1;
+  // the step-control, observable and moment accumulators and the barrier counters restart at zero
+  HIPCHK(c, hipMemsetAsync(c->run_d_err, 0, sizeof(double) * c->run_nsys * 3, stream));
+  HIPCHK(c, hipMemsetAsync(c->run_d_obs, 0, sizeof(double) * c->run_ninst * 18, stream));
+  HIPCHK(c, hipMemsetAsync(c->run_d_mom, 0, sizeof(double) * c->run_ninst * 9, stream));
+  HIPCHK(c, hipMemsetAsync(c->run_d_bar, 0, sizeof(unsigned long long) * c->run_ng, stream));
+  const GroupView<real>* d_groups = reinterpret_cast<const GroupView<real>*>(c->run_d_groups);
+  HIPCHK(c, hipEventRecord(c->ev0, stream));
+  {
+    hipError_t e = launch_dp5<real>(d_groups, P, c->run_grid, c->run_RB, c->run_plan, c->run_fixed, c->run_coop,
+                                    stream, c->run_bs);
+    if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("stepping kernel launch: ") + hipGetErrorString(e));
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, stream));
+  {
+    hipError_t e = launch_energy<real>(d_groups, c->run_d_imap, c->run_ninst, P, c->d_energy, c->run_nmax, stream);
+    if (e != hipSuccess) return fail(c, BPM_EHIP, std::string("energy kernel launch: ") + hipGetErrorString(e));
+  }
+  c->run_t_end = o->t_end;
+  c->run_P.t_end = o->t_end;
   c->run_stream = stream;
   c->run_pending = true;
   c->have_results = false;
@@ -910,6 +980,20 @@ int bpm_run(bpm_ctx* c, const bpm_run_opts* o, void* hip_stream) {
   if (c->insts.empty()) return fail(c, BPM_ESTATE, "bpm_run: no instances");
   hipSetDevice(c->device);
   hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->own_stream;
+  if (o->flags & BPM_FLAG_CONTINUE) {
+    if (!c->run_resumable || c->run_version != c->inst_version)
+      return fail(c, BPM_ESTATE, "bpm_run: BPM_FLAG_CONTINUE needs a previous DP5 run of the same instances");
+    if (o->integrator != c->run_integrator || o->precision != c->run_precision)
+      return fail(c, BPM_EINVAL, "bpm_run: a continued run keeps the integrator and precision of the run it continues");
+    if (o->t_end < c->run_t_end) return fail(c, BPM_EINVAL, "bpm_run: a continued run cannot end before the run it continues");
+    if (o->integrator == BPM_DP5_FIXED) {
+      const double q = c->run_t_end / c->run_dt_fixed;
+      if (o->dt_fixed != c->run_dt_fixed || std::fabs(q - std::round(q)) > 1e-9 * std::max(1.0, q))
+        return fail(c, BPM_EINVAL, "bpm_run: a continued fixed-step run needs the same dt_fixed and a previous end on its grid");
+    }
+    return o->precision == 64 ? resume_typed<double>(c, o, s) : resume_typed<float>(c, o, s);
+  }
+  c->run_resumable = false;
   c->run_rfast = false;
   if (o->integrator == BPM_HEUN) return o->precision == 64 ? run_heun_typed<double>(c, o, s) : run_heun_typed<float>(c, o, s);
   return o->precision == 64 ? run_typed<double>(c, o, s) : run_typed<float>(c, o, s);

@@ -88,19 +88,23 @@ struct Instance {
   bool coupled = false;
 };
 
-// Per-system outputs written by the kernels.
+// Per-system outputs written by the kernels; a continued run starts from them (time, step size
+// and growth cap of the controller, counters).
 struct SysOut {
   int32_t status, pad_;
   double t_reached;
   int64_t n_accept, n_reject;
   double dt_min_used, dt_max_used, max_norm_dev;
+  double dt_next, fac;        // next step size and its growth cap
+  int64_t istep;              // accepted steps (fixed-step time grid index)
 };
 
-// Per-instance outputs.
+// Per-instance outputs (and the crossing state a continued run resumes).
 struct InstOut {
   int32_t crossed, switched;
   double t_sw, mz_soft, mz_hard;
   int64_t n_traj;
+  double prev_t, prev_v;      // last accepted time and hard-layer <m_z>
 };
 
 // Kernel view of one mesh group for a run.
@@ -145,7 +149,7 @@ struct RunParams {
   double t_end, dt0, dt_fixed, rtol, atol, dt_min, temperature;
   int64_t max_steps;
   int32_t save_every, traj_cap;
-  int32_t flags, pad_;
+  int32_t flags, resume;      // resume: continue from sys_out / inst_out and the stored m, k1
   const InstConst* inst;
   const SysView* sys;
   SysOut* sys_out;

@@ -44,8 +44,8 @@ __constant__ double kE[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253
 
 // CSR entries whose gathers are issued together (a whole row in FP32; FP64 halves it to stay in
 // registers)
-template <typename real> struct Gather { static constexpr int W = 24; };
-template <> struct Gather<double> { static constexpr int W = 12; };
+template <typename real, bool kX> struct Gather { static constexpr int W = 24; };
+template <bool kX> struct Gather<double, kX> { static constexpr int W = 12; };
 
 
 // ---------------------------------------------------------------------------------------------
@@ -332,7 +332,7 @@ __device__ __forceinline__ void phase_A(const GroupView<real>& g, const RunParam
     const GLB real* y = ysrc + (size_t)r * 3 * n;
     real ex0 = 0, ex1 = 0, ex2 = 0, bb = 0;
     const int qa = cs.rp[k], qb = cs.rp[k + 1];
-    constexpr int kGather = Gather<real>::W;
+    constexpr int kGather = Gather<real, kX>::W;
     for (int q0 = qa; q0 < qb; q0 += kGather) {
       // all gathers of the row in flight at once (masked entries read the node itself)
       int cj[kGather];
@@ -469,82 +469,104 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
   }
 }
 
-// Symmetric variant for a group owned by one workgroup: only the upper triangle of S is read.
-// Row k contributes S_kl b_l (l >= k) to u_k through the wave reduction and S_kl b_k (l > k) to u_l
-// through LDS atomics; uL (RB x ldS in LDS, after bL) collects u.  The summation order depends on
-// the atomics' order, so this variant is used for FP32 runs only.
+// Symmetric variant for a group owned by one workgroup (FP32): only the 64 x 64 tiles of S on or
+// above the diagonal are read, and each is used twice.  Lane (rg, cq) of the wave that takes tile
+// (I, J) holds rows 64I + 16rg + t (t < 16) and columns 64J + 4cq .. +3 of it (sixteen 16-byte
+// loads in flight per lane) and forms
+//   row sums     u_I += S_IJ b_J                   (every tile, the diagonal tile in full), and
+//   column sums  u_J += S_IJ^T b_I = S_JI b_I      (tiles above the diagonal).
+// Row sums are reduced over the 16 lanes of a row group and column sums over the four row groups
+// by halving exchanges, so that each lane ends with one row (64I + lane) and one column
+// (64J + 4cq + rg), which it adds into u in LDS (uL, RB x ldS after bL).  The order of those LDS
+// additions, and with it the rounding of u, varies from run to run.  Tiles go round-robin over
+// the waves of the workgroup.
 template <typename real, int BS>
 __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, real* bL, int RB) {
+  static_assert(sizeof(real) == 4, "the tiled symmetric product is the FP32 path");
   const int n = g.n, ldS = g.ldS;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   constexpr int nw = BS / 64;
-  constexpr int VEC = 16 / sizeof(real);
-  constexpr int U = 4;
-  constexpr int RMAX = PhaseBShape<real>::RMAX;
-  constexpr int STEP = 64 * VEC;
-  using vec_t = typename std::conditional<sizeof(real) == 4, float4, double2>::type;
-  const GLB real* Sg = glb(g.S);
-  GLB real* __restrict__ ug = glb(g.u);
-  RB = min(RB, RMAX);
-  real* uL = bL + (size_t)RB * ldS;
+  const int rg = lane >> 4, cq = lane & 15;
+  const GLB float* Sg = reinterpret_cast<const GLB float*>(glb(g.S));
+  GLB float* __restrict__ ug = reinterpret_cast<GLB float*>(glb(g.u));
+  const int NB = (n + 63) >> 6;
+  const int ntile = NB * (NB + 1) / 2;
+  RB = min(RB, PhaseBShape<real>::RMAX);
+  float* bLf = reinterpret_cast<float*>(bL);
+  float* uL = bLf + (size_t)RB * ldS;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int rb = 0; rb < g.R; rb += RB) {
     const int rn = min(RB, g.R - rb);
     bool any = false;
     for (int r = rb; r < rb + rn; ++r) any = any || c.active[c.isys[r]];
     if (!any) continue;
     __syncthreads();
-    copy16<BS, 16, false>(reinterpret_cast<uint4*>(bL), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
-                          rn * ldS / VEC);
-    for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) uL[idx] = (real)0;
+    copy16<BS, 16, false>(reinterpret_cast<uint4*>(bLf), reinterpret_cast<const GLB uint4*>(glb(g.b) + (size_t)rb * ldS),
+                          rn * ldS / 4);
+    for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) uL[idx] = 0.f;
     __syncthreads();
-    for (int k = wid; k < n; k += nw) {
-      const GLB real* Srow = Sg + (size_t)k * ldS;
-      real acc[RMAX], bk[RMAX];
+    // tile (I, J) of flat upper-triangle index f = wid, wid + nw, ... (row-major over I <= J)
+    int I = 0, J = wid;
+    while (J >= NB && I < NB) { J -= NB - I - 1; ++I; }
+    for (int f = wid; f < ntile; f += nw) {
+      const int row0 = 64 * I + 16 * rg;
+      const int col0 = 64 * J + 4 * cq;
+      const bool cok = col0 < ldS;   // ldS is a multiple of 4: the whole 16-byte word is in the row
+      float4 sv[16];
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) {
-        acc[r] = 0;
-        bk[r] = r < rn ? bL[r * ldS + k] : (real)0;
+      for (int t = 0; t < 16; ++t) {
+        const int row = row0 + t;
+        sv[t] = (cok && row < n) ? *reinterpret_cast<const GLB float4*>(Sg + (size_t)row * ldS + col0) : z4;
       }
-      const int start = k & ~(VEC - 1);
-      for (int l0 = start + lane * VEC; l0 < ldS; l0 += STEP * U) {
-        vec_t sv[U];
+#pragma unroll 1
+      for (int r = 0; r < rn; ++r) {
+        const float* b = bLf + (size_t)r * ldS;
+        const float4 bj = cok ? *reinterpret_cast<const float4*>(b + col0) : z4;
+        // row sums over this lane's four columns, then over the 16 lanes of the row group
+        float h[16];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int l = l0 + u * STEP;
-          if (l < ldS) sv[u] = *reinterpret_cast<const GLB vec_t*>(Srow + l);
-          else sv[u] = vec_t{};
-        }
+        for (int t = 0; t < 16; ++t) h[t] = sv[t].x * bj.x + sv[t].y * bj.y + sv[t].z * bj.z + sv[t].w * bj.w;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int l = l0 + u * STEP;
-          if (l >= ldS) break;
+        for (int m = 8; m >= 1; m >>= 1) {
+          const bool up = cq & m;
 #pragma unroll
-          for (int q = 0; q < VEC; ++q) {
-            const int col = l + q;
-            if (col < k || col >= n) continue;
-            const real sq = vcomp(sv[u], q);
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-              if (r < rn) {
-                acc[r] += sq * bL[r * ldS + col];
-                if (col > k) atomicAdd(&uL[r * ldS + col], sq * bk[r]);
-              }
-            }
+          for (int j = 0; j < m; ++j) {
+            const float keep = up ? h[j + m] : h[j];
+            const float send = up ? h[j] : h[j + m];
+            h[j] = keep + __shfl_xor(send, m, 64);
           }
         }
-      }
+        if (64 * I + lane < n) atomicAdd(&uL[(size_t)r * ldS + 64 * I + lane], h[0]);
+        if (I < J) {
+          // rows 16rg .. 16rg + 15 of b_I (row0 is a multiple of 16, as is ldS)
+          float bi[16];
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) {
-        if (r < rn) {
-          const real v = wave_sum(acc[r]);
-          if (lane == 0) atomicAdd(&uL[r * ldS + k], v);
+          for (int q = 0; q < 4; ++q) {
+            const float4 v = row0 < ldS ? *reinterpret_cast<const float4*>(b + row0 + 4 * q) : z4;
+            bi[4 * q] = v.x; bi[4 * q + 1] = v.y; bi[4 * q + 2] = v.z; bi[4 * q + 3] = v.w;
+          }
+          float cp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int t = 0; t < 16; ++t) {
+            cp[0] += sv[t].x * bi[t]; cp[1] += sv[t].y * bi[t];
+            cp[2] += sv[t].z * bi[t]; cp[3] += sv[t].w * bi[t];
+          }
+          // over the four row groups (lanes cq + 16 rg): column 4cq + rg stays with lane (rg, cq)
+          const bool g1 = rg & 2, g0 = rg & 1;
+          const float c0 = (g1 ? cp[2] : cp[0]) + __shfl_xor(g1 ? cp[0] : cp[2], 32, 64);
+          const float c1 = (g1 ? cp[3] : cp[1]) + __shfl_xor(g1 ? cp[1] : cp[3], 32, 64);
+          const float cs = (g0 ? c1 : c0) + __shfl_xor(g0 ? c0 : c1, 16, 64);
+          if (col0 + rg < n) atomicAdd(&uL[(size_t)r * ldS + col0 + rg], cs);
         }
       }
+      // next tile of this wave: nw further along the flat index
+      J += nw;
+      while (J >= NB && I < NB) { J -= NB - I - 1; ++I; }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < rn * n; idx += BS) {
       const int r = idx / n, l = idx - r * n;
-      ug[(size_t)(rb + r) * ldS + l] = uL[r * ldS + l];
+      ug[(size_t)(rb + r) * ldS + l] = uL[(size_t)r * ldS + l];
     }
   }
 }
@@ -645,7 +667,7 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
   // demag: -mu0 / V_i (D^T u)_i
   real dx = 0, dy = 0, dz = 0;
   const int qa = cs.rp[k], qb = cs.rp[k + 1];
-  constexpr int kGather = Gather<real>::W;
+  constexpr int kGather = Gather<real, kX>::W;
   for (int q0 = qa; q0 < qb; q0 += kGather) {
     real uq[kGather];
 #pragma unroll
@@ -803,9 +825,17 @@ __device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunPa
   const bool mq = c.any_coupled && threadIdx.x < g.R * 3;
   double mv = 0.0;
   if (mq) mv = acc_ld(&P.mom_acc[((size_t)(g.inst0 + threadIdx.x / 3) * 3 + ev % 3) * 3 + threadIdx.x % 3]);
-  if (SL) phase_B<real, BS, true, kX>(g, c, i0, i1, bL, SL, part, RB);
-  else if (!kX && g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4) phase_B_sym<real, BS>(g, c, bL, RB);
-  else phase_B<real, BS, false, kX>(g, c, i0, i1, bL, nullptr, part, RB);
+  bool done = false;
+  if constexpr (!kX && sizeof(real) == 4) {
+    if (!SL && g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG)) {
+      phase_B_sym<real, BS>(g, c, bL, RB);
+      done = true;
+    }
+  }
+  if (!done) {
+    if (SL) phase_B<real, BS, true, kX>(g, c, i0, i1, bL, SL, part, RB);
+    else phase_B<real, BS, false, kX>(g, c, i0, i1, bL, nullptr, part, RB);
+  }
   if (c.any_coupled) {
     if (mq) c.mom[threadIdx.x / 3][threadIdx.x % 3] = mv;
     __syncthreads();
@@ -874,12 +904,22 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
   GLB real* __restrict__ kg = glb(g.k);
   const long long nfix = kFixed ? (long long)ceil(P.t_end / P.dt_fixed - 1e-9) : 0;
 
-  // ---- init control state
+  // ---- init control state: a fresh run starts at t = 0; a continued run (P.resume) takes the
+  // controller state, counters and crossing state the previous launch left in sys_out / inst_out
   for (int sl = threadIdx.x; sl < g.nsys; sl += BS) {
-    c.t[sl] = 0.0; c.dt[sl] = kFixed ? P.dt_fixed : P.dt0; c.h[sl] = 0.0; c.fac[sl] = 5.0;
-    c.dtmin[sl] = INFINITY; c.dtmax[sl] = 0.0; c.maxdev[sl] = 0.0; c.err[sl] = 0.0;
-    c.istep[sl] = 0; c.nacc[sl] = 0; c.nrej[sl] = 0;
-    c.status[sl] = BPM_OK; c.active[sl] = P.t_end > 0.0 ? 1 : 0; c.last[sl] = 0; c.ninst[sl] = 0;
+    if (P.resume) {
+      const SysOut& so = P.sys_out[g.sys0 + sl];
+      c.t[sl] = so.t_reached; c.dt[sl] = so.dt_next; c.fac[sl] = so.fac;
+      c.dtmin[sl] = so.n_accept ? so.dt_min_used : INFINITY; c.dtmax[sl] = so.dt_max_used;
+      c.maxdev[sl] = so.max_norm_dev; c.istep[sl] = so.istep; c.nacc[sl] = so.n_accept; c.nrej[sl] = so.n_reject;
+      c.status[sl] = so.status; c.active[sl] = (so.status == BPM_OK && so.t_reached < P.t_end) ? 1 : 0;
+    } else {
+      c.t[sl] = 0.0; c.dt[sl] = kFixed ? P.dt_fixed : P.dt0; c.fac[sl] = 5.0;
+      c.dtmin[sl] = INFINITY; c.dtmax[sl] = 0.0; c.maxdev[sl] = 0.0;
+      c.istep[sl] = 0; c.nacc[sl] = 0; c.nrej[sl] = 0;
+      c.status[sl] = BPM_OK; c.active[sl] = P.t_end > 0.0 ? 1 : 0;
+    }
+    c.h[sl] = 0.0; c.err[sl] = 0.0; c.last[sl] = 0; c.ninst[sl] = 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -890,7 +930,13 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
       c.ninst[sl] += 1;
       c.coupled[r] = P.sys[g.sys0 + sl].coupled;
       c.any_coupled |= c.coupled[r];
-      c.crossed[r] = 0; c.ntraj[r] = 0; c.tsw[r] = NAN;
+      if (P.resume) {
+        const InstOut& io = P.inst_out[g.inst0 + r];
+        c.crossed[r] = io.crossed; c.ntraj[r] = io.n_traj; c.tsw[r] = io.t_sw;
+        c.prev_t[r] = io.prev_t; c.prev_v[r] = io.prev_v; c.mzs[r] = io.mz_soft; c.mzh[r] = io.mz_hard;
+      } else {
+        c.crossed[r] = 0; c.ntraj[r] = 0; c.tsw[r] = NAN;
+      }
     }
   }
   __syncthreads();
@@ -910,9 +956,11 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
     __syncthreads();
   }
 
-  // ---- prologue: stage input = m0, observables of m0, first right-hand side
+  // ---- prologue: stage input = m0, observables of m0, first right-hand side (a continued run
+  // keeps m and the first-stage slope k1 of its last accepted step and skips it)
   real* ys0 = g.ys;
   real* ys1 = g.ys + ybuf;
+  if (!P.resume) {
   for (int q = threadIdx.x; q < g.R * 6; q += BS) c.accL[q / 6][q % 6] = 0.0;
   __syncthreads();
   for (int it2 = threadIdx.x; it2 < g.R * nown; it2 += BS) {
@@ -939,9 +987,12 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
     for (int q = threadIdx.x; q < g.R * 3; q += BS)
       if (c.coupled[q / 3]) atomicAdd(&P.mom_acc[((size_t)(g.inst0 + q / 3) * 3 + 0) * 3 + q % 3], c.accL[q / 3][2 + q % 3]);
   group_sync<kX>(gs);
+  }
   // One call site of the field evaluation (its code is large): the evaluation of stage 0 of the
-  // prologue is the first pass of the loop, then stages 1..6 of every attempt.
-  int ev = 0, it = 0, s = 0;
+  // prologue is the first pass of the loop, then stages 1..6 of every attempt.  A continued run
+  // enters the loop past that evaluation (the moment slot of the next stage input is then 1).
+  int ev = P.resume ? 1 : 0, it = 0, s = 0;
+  bool skip0 = P.resume != 0;
   for (;;) {
     if (s == 1) {
       __syncthreads();
@@ -959,18 +1010,18 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         for (int sl = threadIdx.x; sl < g.nsys; sl += BS) acc_st(&P.err_acc[(size_t)(g.sys0 + sl) * 3 + (it + 2) % 3], 0.0);
       }
     }
-    // the moment slot of the next evaluation, filled by the writers of its stage input
-    if (lead && c.any_coupled)
-      for (int r = threadIdx.x; r < g.R; r += BS)
-        for (int d = 0; d < 3; ++d) acc_st(&P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 1) % 3) * 3 + d], 0.0);
-    {
+    if (!skip0) {
+      // the moment slot of the next evaluation, filled by the writers of its stage input
+      if (lead && c.any_coupled)
+        for (int r = threadIdx.x; r < g.R; r += BS)
+          for (int d = 0; d < 3; ++d) acc_st(&P.mom_acc[((size_t)(g.inst0 + r) * 3 + (ev + 1) % 3) * 3 + d], 0.0);
       const real* src = (s & 1) ? ys1 : ys0;
       real* dst = (s & 1) ? ys0 : ys1;
       field_eval<real, kFixed, BS, kL, kX>(g, P, c, icL, dipL, gs, i0, i1, s, src, dst, it, ev++, bL, SL, part, RB, cs);
     }
     if (s == 0) {
-      // initial observables, crossing state, first trajectory sample
-      for (int r = threadIdx.x; r < g.R; r += BS) {
+      // initial observables, crossing state, first trajectory sample (fresh runs)
+      for (int r = threadIdx.x; r < g.R && !skip0; r += BS) {
         double ob[6];
 #pragma unroll
         for (int d = 0; d < 6; ++d) ob[d] = acc_ld(&P.obs_acc[((size_t)(g.inst0 + r) * 3 + 2) * 6 + d]);
@@ -980,6 +1031,7 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         if (vh <= 0.0) { c.crossed[r] = 1; c.tsw[r] = 0.0; }
         if (lead) save_sample<real, BS>(g, P, c, icL, r, 0.0, 0.0, 0.0, ob);
       }
+      skip0 = false;
       for (int q = threadIdx.x; q < g.R * 3; q += BS) c.mom[q / 3][q % 3] = 0.0;
       __syncthreads();
       plan_attempt<kFixed, BS>(P, c, g.nsys, nfix);
@@ -1034,7 +1086,9 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
         c.dtmin[sl] = fmin(c.dtmin[sl], h); c.dtmax[sl] = fmax(c.dtmax[sl], h);
         if (!kFixed) {
           const double fac = err == 0.0 ? c.fac[sl] : fmin(c.fac[sl], fmax(0.2, 0.9 * pow(err, -0.2)));
-          c.dt[sl] = h * fac;
+          // a step shortened to land on t_end hands a continued run the step planned before the
+          // shortening when that is longer (c.dt still holds it); a run that ends here is unaffected
+          c.dt[sl] = c.last[sl] ? fmax(h * fac, c.dt[sl]) : h * fac;
           c.fac[sl] = 5.0;
         }
         if (c.last[sl]) c.active[sl] = 0;
@@ -1130,21 +1184,21 @@ __device__ __forceinline__ void dp5_body(const GroupView<real>& g, const RunPara
       SysOut& o = P.sys_out[g.sys0 + sl];
       o.status = c.status[sl]; o.t_reached = c.t[sl]; o.n_accept = c.nacc[sl]; o.n_reject = c.nrej[sl];
       o.dt_min_used = c.nacc[sl] ? c.dtmin[sl] : 0.0; o.dt_max_used = c.dtmax[sl]; o.max_norm_dev = c.maxdev[sl];
+      o.dt_next = c.dt[sl]; o.fac = c.fac[sl]; o.istep = c.istep[sl];
     }
     for (int r = threadIdx.x; r < g.R; r += BS) {
       InstOut& o = P.inst_out[g.inst0 + r];
       o.crossed = c.crossed[r]; o.t_sw = c.tsw[r]; o.mz_soft = c.mzs[r]; o.mz_hard = c.mzh[r];
       o.switched = c.mzh[r] < 0.0; o.n_traj = c.ntraj[r];
+      o.prev_t = c.prev_t[r]; o.prev_v = c.prev_v[r];
     }
   }
 }
 
 
 template <typename real, bool kFixed, int BS, bool kL, bool kX>
-__global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restrict__ groups,
-                                                 RunParams P, int RB, LdsPlan LP) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ Ctl c;
+__device__ __forceinline__ void dp5_entry(const GroupView<real>* __restrict__ groups, const RunParams& P, int RB,
+                                          const LdsPlan& LP, unsigned char* smem_raw, Ctl& c) {
   const int2 gm = P.wg_map[blockIdx.x];
   const GroupView<real> g = groups[gm.x];
   const int w = gm.y;
@@ -1219,6 +1273,14 @@ __global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restri
     __syncthreads();
     dp5_body<real, kFixed, BS, false, kX>(g, P, c, icL, dipL, w, bL, SL, part, RB, cs);
   }
+}
+
+template <typename real, bool kFixed, int BS, bool kL, bool kX>
+__global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restrict__ groups,
+                                                 RunParams P, int RB, LdsPlan LP) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ Ctl c;
+  dp5_entry<real, kFixed, BS, kL, kX>(groups, P, RB, LP, smem_raw, c);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -334,10 +334,17 @@ def sample_designs(n: int, seed: int = 2, fixed_alpha_rise: bool = True, log_pri
     return x
 
 
-def design_node_target(x: np.ndarray, density: float = 1.0e27) -> int:
-    """Node count proportional to island volume (1 node per nm^3), clipped to [300, 3000]."""
+# Node density of the batched designs: the largest island of the design box (d = 12 nm, t_soft +
+# t_hard = 16 nm, 1809.6 nm^3) gets 3000 nodes; the count is proportional to the volume and
+# clipped to [300, 3000] (the smallest islands, 113 nm^3, would otherwise get ~190).
+DESIGN_NODES_MIN, DESIGN_NODES_MAX = 300, 3000
+DESIGN_NODE_DENSITY = DESIGN_NODES_MAX / (math.pi * (0.5 * DESIGN_HI[0]) ** 2 * (DESIGN_HI[1] + DESIGN_HI[2]))
+
+
+def design_node_target(x: np.ndarray, density: float = DESIGN_NODE_DENSITY) -> int:
+    """Node count proportional to island volume, clipped to [300, 3000]."""
     vol = math.pi * (x[0] / 2) ** 2 * (x[1] + x[2])
-    return int(min(3000, max(300, round(density * vol))))
+    return int(min(DESIGN_NODES_MAX, max(DESIGN_NODES_MIN, round(density * vol))))
 
 
 def design_inputs(x: np.ndarray, seed: int = 0):
@@ -349,6 +356,33 @@ def design_inputs(x: np.ndarray, seed: int = 0):
     fld = Field(kind=FIELD_UNIFORM, B_peak=x[9], dir=(math.sin(psi), 0.0, -math.cos(psi)),
                 t_rise=x[11])
     return mesh, mat, fld
+
+
+def _design_inputs_job(args):
+    x, seed = args
+    return design_inputs(x, seed)
+
+
+def design_inputs_many(X: np.ndarray, seeds=None, workers: int = 0):
+    """design_inputs for every row of X (mesh seed = row index unless seeds is given), meshed by a
+    pool of worker processes (workers = 0: up to 16, bounded by the CPUs this process may use).
+    Call it before any GPU work in the process: the workers are started with 'spawn'."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    X = np.asarray(X, dtype=np.float64)
+    seeds = list(range(X.shape[0])) if seeds is None else list(seeds)
+    jobs = [(X[q], int(seeds[q])) for q in range(X.shape[0])]
+    if workers <= 0:
+        try:
+            avail = len(os.sched_getaffinity(0))
+        except AttributeError:
+            avail = os.cpu_count() or 1
+        workers = max(1, min(16, avail))
+    if workers == 1 or len(jobs) < 32:
+        return [_design_inputs_job(j) for j in jobs]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_design_inputs_job, jobs, chunksize=16))
 
 
 def random_unit_m(n: int, seed: int, cone: float = math.pi) -> np.ndarray:

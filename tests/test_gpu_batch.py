@@ -1,0 +1,205 @@
+"""GPU parity of the batched path (independent uneven islands, one workgroup each) and of
+continued runs, through the C ABI.
+
+* The demag product that reads only the upper triangle of S (64 x 64 tiles, FP32) against the
+  FP64 oracle and against the full product, element by element, on islands of 266-2898 nodes
+  (ragged last tiles, the largest island of the design box).
+* Continued runs (BPM_FLAG_CONTINUE) against one run: identical for fixed steps on their grid,
+  the same switching for adaptive steps; misuse rejected.
+* 64 designs of the 4096-island batch, FP32 adaptive in one launch, against the FP64 oracle's
+  switching time and field (stored by tests/golden/make_cfg2_switching.py, which calls only the
+  oracle).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1603_09493_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_switching.json")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1603_09493_amd import bpm
+    c = bpm.Context(0)
+    yield c
+    c.close()
+
+
+def _case(name, **kw):
+    print(f"[gpu-case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _batch_rows():
+    """Rows of the 4096-design batch: the smallest and largest island and two whose node counts
+    leave ragged 64-node tiles."""
+    X = I.sample_designs(4096, seed=2)
+    n = np.array([I.design_node_target(x) for x in X])
+    order = np.argsort(n, kind="stable")
+    rows = [int(order[0]), int(order[-1])]
+    for q in order[len(order) // 3:]:
+        if n[q] % 64 not in (0, 63) and len(rows) < 4 and int(q) not in rows:
+            rows.append(int(q))
+    return X, rows
+
+
+def test_tiled_symmetric_product_against_oracle(ctx, oracle_mod):
+    """FP32 fixed-step DP5 (200 steps of 5 fs) of four batch islands in one launch, one workgroup
+    each, upper-triangle demag product, from seeded states within 0.6 rad of +z: every node within
+    1e-4 of the FP64 oracle, and within 2e-5 of the same launch with the full product."""
+    from paper_1603_09493_amd import bpm
+    X, rows = _batch_rows()
+    T, dt = 1e-12, 5e-15
+    ctx.clear_instances()
+    cases = []
+    for q in rows:
+        mesh, mat, fld = I.design_inputs(X[q], seed=q)
+        om = oracle_mod.OracleMesh(mesh)
+        S = om.demag_S()
+        mid = ctx.mesh_add(mesh, S)
+        m0 = I.random_unit_m(mesh.n, seed=100 + q, cone=0.6)
+        cases.append((mesh, mat, fld, om, S, ctx.instance_add(mid, mat, fld, m0=m0), m0))
+    _case("tiled-symmetric", sizes=[c[0].n for c in cases])
+    assert min(c[0].n for c in cases) < 300 and max(c[0].n for c in cases) > 2800
+    got = {}
+    for name, flags in (("sym", bpm.FLAG_SYMMETRIC_DEMAG), ("full", 0)):
+        ctx.run(t_end=T, precision=32, integrator=bpm.DP5_FIXED, dt_fixed=dt, wg_per_group=1, flags=flags)
+        ctx.sync()
+        assert ctx.last_run_info()["wg_per_group"] == 1
+        got[name] = [ctx.get_m(c[5], c[0].n) for c in cases]
+        assert all(r["status"] == 0 and r["n_accept"] == 200 for r in ctx.results([c[5] for c in cases]))
+    for (mesh, mat, fld, om, S, iid, m0), ms, mf in zip(cases, got["sym"], got["full"]):
+        mo, ro, _ = om.run(S, [mat], [fld], dict(t_end=T, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt), m0=m0)
+        assert np.abs(mo[0] - m0).max() > 1e-2          # the state moved
+        assert np.abs(ms - mo[0]).max() <= 1e-4, (mesh.n, np.abs(ms - mo[0]).max())
+        assert np.abs(ms - mf).max() <= 2e-5, (mesh.n, np.abs(ms - mf).max())
+
+
+def test_continued_fixed_step_run_is_identical(ctx, oracle_mod):
+    """FP64 fixed step on the single-island workload: 0 -> 1 ps -> 2 ps -> 3 ps in three runs
+    takes the same 300 steps as one 3 ps run and lands on the same state and trajectory (to the
+    rounding of the grid time at the splits), and both match the oracle."""
+    from paper_1603_09493_amd import bpm
+    mesh, mat, fld = I.single_island_workload()
+    om = oracle_mod.OracleMesh(mesh)
+    S = om.demag_S()
+    dt = 10e-15
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh, S)
+    iid = ctx.instance_add(mid, mat, fld)
+    _case("continue-fixed", n=mesh.n)
+    kw = dict(precision=64, integrator=bpm.DP5_FIXED, dt_fixed=dt, save_every=25, traj_cap=64)
+    ctx.run(t_end=3e-12, **kw)
+    ctx.sync()
+    m1, r1, t1 = ctx.get_m(iid, mesh.n), ctx.results([iid])[0], ctx.trajectory(iid, 64)
+    for k, T in enumerate((1e-12, 2e-12, 3e-12)):
+        ctx.run(t_end=T, flags=bpm.FLAG_CONTINUE if k else 0, **kw)
+        ctx.sync()
+    m3, r3, t3 = ctx.get_m(iid, mesh.n), ctx.results([iid])[0], ctx.trajectory(iid, 64)
+    assert r3["status"] == r1["status"] == 0, (r1, r3)
+    assert r3["n_accept"] == r1["n_accept"] == 300, (r1["n_accept"], r3["n_accept"])
+    assert abs(r3["t_reached"] - 3e-12) <= 1e-24 and abs(r1["t_reached"] - 3e-12) <= 1e-24
+    assert np.abs(m1 - m3).max() <= 1e-13, np.abs(m1 - m3).max()
+    assert t1.shape == t3.shape, (t1.shape, t3.shape)
+    assert np.abs(t1 - t3).max() <= 1e-13, np.abs(t1 - t3).max(axis=0)
+    mo, ro, _ = om.run(S, [mat], [fld], dict(t_end=3e-12, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt))
+    assert np.abs(m3 - mo[0]).max() <= 1e-9
+
+
+def test_continued_adaptive_batch_switches_alike(ctx):
+    """FP32 adaptive, upper-triangle product, eight batch islands driven hard enough to switch:
+    ten continued 20 ps slices give the same switching as one 0.2 ns run (the only difference is
+    the step shortened to land on each slice end)."""
+    from paper_1603_09493_amd import bpm
+    X = I.sample_designs(8, seed=21)
+    X[:, 9] = 2.0                        # peak field at the top of the range
+    X[:, 5:7] = np.minimum(X[:, 5:7], 0.6e6)
+    ctx.clear_instances()
+    ids = []
+    for q, x in enumerate(X):
+        mesh, mat, fld = I.design_inputs(x, seed=q)
+        ids.append(ctx.instance_add(ctx.mesh_add(mesh, keep=2), mat, fld))
+    _case("continue-adaptive", islands=len(ids))
+    kw = dict(precision=32, rtol=1e-5, flags=bpm.FLAG_SYMMETRIC_DEMAG)
+    ctx.run(t_end=0.2e-9, **kw)
+    ctx.sync()
+    one = ctx.results(ids)
+    for k in range(10):
+        ctx.run(t_end=0.2e-9 * (k + 1) / 10, **dict(kw, flags=kw["flags"] | (bpm.FLAG_CONTINUE if k else 0)))
+        ctx.sync()
+    sl = ctx.results(ids)
+    print("[continue-adaptive]", [(a["switched"], a["t_sw"], b["t_sw"], a["n_accept"], b["n_accept"])
+                                  for a, b in zip(one, sl)], flush=True)
+    assert sum(r["switched"] for r in one) >= 4
+    for a, b in zip(one, sl):
+        assert a["status"] == b["status"] == 0 and abs(b["t_reached"] - 0.2e-9) <= 1e-21, (a, b)
+        assert a["switched"] == b["switched"], (a, b)
+        if a["switched"]:
+            assert abs(a["t_sw"] / b["t_sw"] - 1) <= 1e-3, (a, b)
+        assert abs(a["mz_hard"] - b["mz_hard"]) <= 5e-3, (a, b)
+        assert abs(a["n_accept"] - b["n_accept"]) <= 20, (a, b)
+
+
+def test_continue_misuse_is_rejected(ctx):
+    from paper_1603_09493_amd import bpm
+    mesh, mat, fld = I.single_island_workload(n_target=300)
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh)
+    iid = ctx.instance_add(mid, mat, fld)
+    ctx.run(t_end=1e-12, precision=64, integrator=bpm.DP5_FIXED, dt_fixed=10e-15)
+    ctx.sync()
+    for bad, code in ((dict(t_end=0.5e-12), bpm.BPM_EINVAL),
+                      (dict(t_end=2e-12, precision=32), bpm.BPM_EINVAL),
+                      (dict(t_end=2e-12, dt_fixed=7e-15), bpm.BPM_EINVAL)):
+        kw = dict(precision=64, integrator=bpm.DP5_FIXED, dt_fixed=10e-15, flags=bpm.FLAG_CONTINUE)
+        kw.update(bad)
+        with pytest.raises(bpm.BpmError) as e:
+            ctx.run(**kw)
+        assert e.value.code == code
+    assert ctx.results([iid])[0]["t_reached"] == 1e-12   # the failed calls left the results alone
+    ctx.instance_add(mid, mat, fld)      # the instance set changed
+    with pytest.raises(bpm.BpmError) as e:
+        ctx.run(t_end=2e-12, precision=64, integrator=bpm.DP5_FIXED, dt_fixed=10e-15, flags=bpm.FLAG_CONTINUE)
+    assert e.value.code == bpm.BPM_ESTATE
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="tests/golden/cfg2_switching.json not generated")
+def test_batch_switching_parity_64_designs():
+    """64 designs of the batch (266-2898 nodes) in one FP32 adaptive launch, one workgroup per
+    island, upper-triangle demag product, 0.3 ns: the switched flag agrees with the FP64 oracle
+    wherever the oracle's final hard-layer <m_z> is clear of zero, and the switching time and
+    field agree within 1 %."""
+    from paper_1603_09493_amd import bpm
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    X = I.sample_designs(4096, seed=2)
+    c = bpm.Context(0)
+    try:
+        ids = []
+        for d in gold["designs"]:
+            mesh, mat, fld = I.design_inputs(X[d["row"]], seed=d["row"])
+            assert mesh.n == d["n"]
+            ids.append(c.instance_add(c.mesh_add(mesh, keep=2), mat, fld))
+        _case("batch-64", sizes=f"{min(d['n'] for d in gold['designs'])}-{max(d['n'] for d in gold['designs'])}")
+        c.run(t_end=gold["t_end"], precision=32, rtol=1e-5, flags=bpm.FLAG_SYMMETRIC_DEMAG)
+        c.sync()
+        assert c.last_run_info()["wg_per_group"] == 1
+        res = c.results(ids)
+    finally:
+        c.close()
+    n_sw = 0
+    for d, r in zip(gold["designs"], res):
+        assert r["status"] == 0
+        if abs(d["mz_hard"]) > 0.2:
+            assert bool(r["switched"]) == bool(d["switched"]), d
+        if d["switched"] and r["switched"]:
+            n_sw += 1
+            assert abs(r["t_sw"] / d["t_sw"] - 1) <= 0.01, (d, r["t_sw"])
+            assert abs(r["B_sw"] / d["B_sw"] - 1) <= 0.01, (d, r["B_sw"])
+    assert n_sw >= 16

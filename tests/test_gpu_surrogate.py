@@ -13,6 +13,10 @@ def _case(name, **kw):
     print(f"[gpu-case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
 
 
+def _progress(msg):
+    print(f"[surrogate] {msg}", flush=True)
+
+
 def test_surrogate_trains_and_screens_better_than_random():
     import torch
     from paper_1603_09493_amd import bpm
@@ -21,7 +25,7 @@ def test_surrogate_trains_and_screens_better_than_random():
     n_train, n_test, t_end = 896, 128, 0.3e-9
     x = SG.sample(n_train + n_test, seed=12)
     _case("surrogate-label", n=x.shape[0])
-    lab = SG.label_designs(ctx, x, t_end=t_end)
+    lab = SG.label_designs(ctx, x, t_end=t_end, progress=_progress)
     assert np.all(lab.status == 0)
     frac = lab.switched.mean()
     assert 0.1 < frac < 0.95, frac
@@ -56,8 +60,8 @@ def test_surrogate_trains_and_screens_better_than_random():
     xr = SG.sample(4000, seed=77)
     xr = xr[SG.stability(xr) >= min_stab][:96]
     assert xr.shape[0] == 96
-    lab_p = SG.label_designs(ctx, xp, t_end=t_end)
-    lab_r = SG.label_designs(ctx, xr, t_end=t_end)
+    lab_p = SG.label_designs(ctx, xp, t_end=t_end, progress=_progress)
+    lab_r = SG.label_designs(ctx, xr, t_end=t_end, progress=_progress)
     hit_p, hit_r = lab_p.switched.mean(), lab_r.switched.mean()
     print(f"[surrogate] screen 200k in {secs*1e3:.1f} ms; solver-verified switching: picks {hit_p:.2f} "
           f"vs random {hit_r:.2f}", flush=True)
