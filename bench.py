@@ -118,6 +118,19 @@ def cpu_baseline(rows, slice_s, cores):
                       f"{wall:.1f} s wall"}
 
 
+def copy_calibration(mib, reps=3):
+    """Plain device copies of known size, for scaling the profiler's FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}
+
+
 def surrogate_leg(ctx, rows, res, n_test=512, n_cand=1_000_000, k=10_000, epochs=100):
     """Trains the MLP on the batch's own solver labels (switched flag, switching time and field
     after the timed window), reports the held-out switching-field error and times 1M-candidate
@@ -191,6 +204,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--full-demag", action="store_true", help="read all of S (default: its upper triangle)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run three device copies of this many MiB (scales the profiler's byte counters)")
+    ap.add_argument("--cpu-slice-ps", type=float, default=16.0, help="simulated time per oracle island (ps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -318,6 +334,8 @@ def main():
     emit(stop)
     log(f"value {out['value']:.3f} island-ns/s, HBM {out['roofline']['frac']:.3f} of peak")
     res = ctx.results(ids)
+    if args.copy_calib > 0:
+        out["copy_calibration"] = copy_calibration(args.copy_calib)
     if not args.no_surrogate:
         try:
             out["surrogate"] = surrogate_leg(ctx, rows, res)
@@ -332,7 +350,7 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         try:
-            cb = cpu_baseline(rows, 2e-12, cores)
+            cb = cpu_baseline(rows, args.cpu_slice_ps * 1e-12, cores)
             cb["nproc"] = cores
             cb["cpu_model"] = cpu_model
             out["cpu_baseline"] = cb
