@@ -128,6 +128,24 @@ def test_fp64_fixed_step_trajectory_parity(ctx, cfg0, oracle_mod, wg, threads, s
     assert abs(rg[0]["energy"] - ro[0]["energy"]) <= 1e-9 * abs(ro[0]["energy"])
 
 
+def test_fp64_fixed_step_parity_full_window(ctx, cfg0, oracle_mod):
+    """The single-island workload over its whole 0.3 ns (30000 steps of 10 fs, through the ramp
+    and the reversal of the soft layer): every node within 1e-9 of the oracle.  The oracle run
+    against itself from m0 + 1e-15 noise stays far below that bar over this window
+    (tests/golden/parity_floor.txt)."""
+    mesh, mat, fld, om, S = cfg0
+    T, dt = 0.3e-9, 10e-15
+    _case_floor = open(__file__.rsplit("/", 1)[0] + "/golden/parity_floor.txt").read().split("\n")
+    floor = max(float(l.split()[1]) for l in _case_floor if l and not l.startswith("#"))
+    assert floor < 1e-11, floor
+    _print_case("fp64-fixed-0.3ns", n=mesh.n, steps=int(T / dt))
+    mo, ro, _ = om.run(S, [mat], [fld], dict(t_end=T, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt))
+    mg, rg, _ = _run_gpu(ctx, mesh, S, [mat], [fld], t_end=T, precision=64, integrator=1, dt_fixed=dt)
+    assert rg[0]["status"] == 0 and rg[0]["n_accept"] == ro[0]["n_accept"] == 30000
+    assert np.abs(mg[0] - mo[0]).max() <= 1e-9, np.abs(mg[0] - mo[0]).max()
+    assert abs(rg[0]["mz_soft"] - ro[0]["mz_soft"]) <= 1e-9
+
+
 def test_fp64_adaptive_parity(ctx, cfg0, oracle_mod):
     """rtol 1e-6 adaptive run of the single-island workload over 0.1 ns: same step sequence."""
     mesh, mat, fld, om, S = cfg0

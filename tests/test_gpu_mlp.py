@@ -1,9 +1,9 @@
 """GPU parity of the surrogate MLP, the design sampler and the top-k against the CPU oracle.
 
 Bars: sampler and top-k bit-exact (integer/index work, and the sampler's FP32 values are exact
-functions of the Philox words); MLP forward and gradients within the BF16 tolerance (every GEMM
-operand rounded to bf16 on both sides; the GPU accumulates in FP32, the oracle in FP64, and a
-bf16 rounding of an activation can land on the other side of a tie).
+functions of the Philox words); MLP forward and gradients element by element within the BF16
+tolerance (every GEMM operand rounded to bf16 on both sides; the GPU accumulates in FP32, the
+oracle in FP64, and a bf16 rounding of an activation can land on the other side of a tie).
 """
 import numpy as np
 import pytest
@@ -62,9 +62,12 @@ def test_mlp_predict_matches_oracle(ctx, torch_mod):
     Y = Yd.cpu().numpy()
     Yr, _ = OM.forward(th.astype(np.float64), X.astype(np.float64))
     scale = np.abs(Yr).max(0)
-    err = np.abs(Y - Yr).max(0) / scale
-    assert np.all(err < 2e-2), err
-    assert np.median(np.abs(Y - Yr) / scale) < 2e-3
+    # every output: within 1 % of itself plus 0.3 % of its column's scale (a bf16 tie that rounds
+    # the other way moves an output by about 2^-9 of the largest terms feeding it)
+    err = np.abs(Y - Yr)
+    bound = 1e-2 * np.abs(Yr) + 3e-3 * scale
+    assert np.all(err <= bound), (np.argwhere(err > bound)[:5], (err / bound).max())
+    assert np.median(err / scale) < 2e-3
     net.close()
 
 
@@ -88,8 +91,16 @@ def test_mlp_gradients_match_oracle(ctx, torch_mod):
         ni, no = OM.SIZES[i], OM.SIZES[i + 1]
         for blk in (slice(off, off + ni * no), slice(off + ni * no, off + ni * no + no)):
             a, b = g[blk].astype(np.float64), gr[blk]
-            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-            assert rel < 5e-3, (i, rel)
+            rms = np.sqrt(np.mean(b * b))
+            # element by element: within 3 % of itself plus 1 % of the block's RMS, and the
+            # typical element far closer (bf16 ties rounded differently in FP32 and FP64
+            # accumulation account for the spread)
+            err = np.abs(a - b)
+            bound = 3e-2 * np.abs(b) + 1e-2 * rms
+            assert np.all(err <= bound), (i, np.argwhere(err > bound)[:5].ravel(), (err / bound).max())
+            big = np.abs(b) > rms
+            assert np.median(err[big] / np.abs(b[big])) < 2e-3, (i, np.median(err[big] / np.abs(b[big])))
+            assert np.linalg.norm(a - b) / np.linalg.norm(b) < 5e-3
         off += ni * no + no
     net.close()
 
