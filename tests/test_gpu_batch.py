@@ -187,7 +187,9 @@ def test_batch_switching_parity_64_designs():
             assert mesh.n == d["n"]
             ids.append(c.instance_add(c.mesh_add(mesh, keep=2), mat, fld))
         _case("batch-64", sizes=f"{min(d['n'] for d in gold['designs'])}-{max(d['n'] for d in gold['designs'])}")
-        c.run(t_end=gold["t_end"], precision=32, rtol=1e-5, flags=bpm.FLAG_SYMMETRIC_DEMAG)
+        # one workgroup per island, as in the 4096-island launch (64 groups alone would get a
+        # cooperative share of the GPU each)
+        c.run(t_end=gold["t_end"], precision=32, rtol=1e-5, flags=bpm.FLAG_SYMMETRIC_DEMAG, wg_per_group=1)
         c.sync()
         assert c.last_run_info()["wg_per_group"] == 1
         res = c.results(ids)
