@@ -265,6 +265,16 @@ int bpm_sample_designs(bpm_ctx* ctx, uint64_t seed, int64_t n, float* X, void* h
 /* Indices of the k largest scores, ordered by (score descending, index ascending); NaN ranks
  * lowest.  0 < k <= min(n, 16384), n < 2^31.  idx: device int64 [k]. */
 int bpm_topk(bpm_mlp* net, const float* score, int64_t n, int64_t k, int64_t* idx, void* hip_stream);
+/* Allocation-free variant of bpm_topk, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same selection,
+ * order and tie rule, with no hipMalloc, hipFree or other allocation.  Its scratch (histogram,
+ * selection state, candidates, per-block tie counts) is one fixed area of 394496 bytes in device
+ * memory per GPU, held by the library until the process ends; it is cleared by the call's own
+ * kernels.  score: device [n]; idx: device int64 [k]; work is queued on hip_stream (NULL = the
+ * context's stream).  Limits: 0 < k <= min(n, 16384), n <= 67108864 (BPM_EINVAL beyond).  Every
+ * call on one GPU uses that GPU's one area: calls that overlap in time on the same GPU (other
+ * streams, contexts or threads) race and must be serialised by the caller. */
+int bpm_topk_noalloc(bpm_ctx* ctx, const float* score, int64_t n, int64_t k, int64_t* idx, void* hip_stream);
 /* One screening round: sample n designs uniformly in the box [lo, hi] (host [12], finite lo < hi;
  * the uniforms u as bpm_sample_designs, x = lo + (hi - lo) u), write their network inputs to X
  * (log coordinates 2 log(x/lo) / log(hi/lo) - 1 where lo > 0, else 2u - 1), predict, score =

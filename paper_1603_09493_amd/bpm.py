@@ -79,6 +79,7 @@ SYMBOLS = [
 EXTRA_SYMBOLS = [
     "bpm_mlp_num_params", "bpm_mlp_create", "bpm_mlp_destroy", "bpm_mlp_set_params", "bpm_mlp_get_params",
     "bpm_mlp_predict", "bpm_mlp_grads", "bpm_mlp_train_step", "bpm_sample_designs", "bpm_topk", "bpm_screen",
+    "bpm_topk_noalloc",
 ]
 
 _lib = None
@@ -133,6 +134,7 @@ def lib():
     L.bpm_sample_designs.argtypes = [P, C.c_uint64, I64, P, P]
     L.bpm_topk.argtypes = [P, P, I64, I64, P, P]
     L.bpm_screen.argtypes = [P, C.c_uint64, I64, I64, P, P, D, P, P, P, P, P]
+    L.bpm_topk_noalloc.argtypes = [P, P, I64, I64, P, P]
     for name in SYMBOLS + EXTRA_SYMBOLS:
         fn = getattr(L, name)
         if name not in ("bpm_destroy", "bpm_last_error", "bpm_mlp_destroy"):
@@ -399,6 +401,14 @@ class Mlp:
         with _ts(stream) as st:
             self.ctx._check(self.L.bpm_screen(self.h, C.c_uint64(int(seed)), int(n), int(k), _p(lo), _p(hi),
                                               float(min_stability), _dp(X), _dp(Y), _dp(score), _dp(idx), st))
+
+
+def topk_noalloc(ctx: Context, score, k, idx, n=None, stream=None):
+    """bpm_topk_noalloc: indices of the k largest of n device scores into the device int64 idx,
+    with the library's fixed scratch area (no allocation)."""
+    n = score.shape[0] if n is None else n
+    with _ts(stream) as st:
+        ctx._check(ctx.L.bpm_topk_noalloc(ctx.h, _dp(score), int(n), int(k), _dp(idx), st))
 
 
 def sample_designs(ctx: Context, seed, n, X, stream=None):

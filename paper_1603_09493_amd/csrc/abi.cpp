@@ -157,6 +157,9 @@ int bpm_create(bpm_ctx** out, int device) {
     delete c;
     return BPM_EHIP;
   }
+  // device address of this GPU's scratch area of the allocation-free top-k (a failure here is
+  // retried, and reported, by bpm_topk_noalloc)
+  (void)topk_scratch_init(device);
   if (const char* p = std::getenv("BPM_TUNE_CACHE")) {
     c->tune_path = p;
     std::ifstream f(p);
@@ -1356,6 +1359,19 @@ int bpm_topk(bpm_mlp* M, const float* score, int64_t n, int64_t k, int64_t* idx,
   hipSetDevice(c->device);
   hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
   HIPCHK(c, topk_select(score, (long)n, (long)k, idx, M->sc, s));
+  return BPM_OK;
+}
+
+int bpm_topk_noalloc(bpm_ctx* c, const float* score, int64_t n, int64_t k, int64_t* idx, void* stream) {
+  if (!c) return BPM_EINVAL;
+  if (!score || !idx || n <= 0 || k <= 0 || k > n || k > kTopkMax)
+    return fail(c, BPM_EINVAL, "bpm_topk_noalloc: need 0 < k <= min(n, 16384)");
+  if (n > kTopkNoAllocMaxN)
+    return fail(c, BPM_EINVAL, "bpm_topk_noalloc: n exceeds the " + std::to_string(kTopkNoAllocMaxN) +
+                                   " scores its fixed scratch area holds (use bpm_topk)");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : c->own_stream;
+  HIPCHK(c, topk_select_noalloc(score, (long)n, (long)k, idx, c->device, s));
   return BPM_OK;
 }
 

@@ -50,6 +50,11 @@ struct ScreenScratch {
   long blk_cap = 0;
 };
 constexpr long kTopkMax = 16384;
+constexpr long kTopkNoAllocMaxN = 1L << 26;          // scores per allocation-free selection
+constexpr size_t kTopkNoAllocScratchBytes = 394496;  // its scratch area per GPU
+constexpr int kMaxDevices = 64;
+hipError_t topk_scratch_init(int device);            // the calling thread's current device
+hipError_t topk_select_noalloc(const float* score, long n, long k, int64_t* idx, int device, hipStream_t s);
 hipError_t sample_designs(uint64_t seed, long n, float* X, hipStream_t s);
 hipError_t design_features(float* X, long n, const double* lo, const double* hi, hipStream_t s);
 hipError_t topk_select(const float* score, long n, long k, int64_t* idx, ScreenScratch& sc, hipStream_t s);

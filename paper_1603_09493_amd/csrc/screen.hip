@@ -7,6 +7,8 @@
 #include <cmath>
 
 #include "bpm_internal.h"
+#include <mutex>
+
 #include "mlp_internal.h"
 
 namespace bpm {
@@ -255,6 +257,78 @@ __global__ void sort_out_kernel(long k, const unsigned long long* __restrict__ c
       __syncthreads();
     }
   for (long i = threadIdx.x; i < k; i += blockDim.x) idx[i] = (int64_t)(uint32_t)~(uint32_t)(sk[i] & 0xffffffffull);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free top-k: the same kernels on a fixed scratch area in device memory that the library
+// holds for the whole process (one copy per GPU), for callers that cannot allocate.
+// ---------------------------------------------------------------------------------------------
+constexpr long kTopkNoAllocBlk = kTopkNoAllocMaxN / kTieBlock;            // per-block tie counts
+constexpr size_t kScratchHist = 0;                                        // uint32 [256]
+constexpr size_t kScratchState = kScratchHist + 256 * sizeof(uint32_t);   // uint32 [16]
+constexpr size_t kScratchCand = kScratchState + 16 * sizeof(uint32_t);    // uint64 [kTopkMax]
+constexpr size_t kScratchBlk = kScratchCand + kTopkMax * sizeof(unsigned long long);   // uint32 [blk]
+constexpr size_t kScratchBytes = (kScratchBlk + kTopkNoAllocBlk * sizeof(uint32_t) + 255) / 256 * 256;
+static_assert(kScratchBytes == kTopkNoAllocScratchBytes, "scratch size stated in the header");
+static_assert(kScratchCand % 8 == 0 && kScratchBlk % 4 == 0, "aligned sub-arrays");
+
+// Host code must not pass this name to a kernel: it is a host-side stand-in.  The device address of
+// each GPU's copy comes from hipGetSymbolAddress (scratch_dev below).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t topk_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_dev[device] = p;
+  return hipSuccess;
+}
+
+// state of a selection: prefix 0, mask 0, k remaining = k, gather count 0; histogram cleared (a
+// kernel rather than a memset, so that the sequence can be recorded in a graph)
+__global__ void topk_reset_kernel(uint32_t* __restrict__ hist, uint32_t* __restrict__ state, uint32_t k) {
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
+  if (threadIdx.x < 16) state[threadIdx.x] = threadIdx.x == 2 ? k : 0u;
+}
+
+hipError_t topk_select_noalloc(const float* score, long n, long k, int64_t* idx, int device, hipStream_t s) {
+  if (n <= 0 || n > kTopkNoAllocMaxN || k <= 0 || k > n || k > kTopkMax) return hipErrorInvalidValue;
+  hipError_t e = topk_scratch_init(device);
+  if (e != hipSuccess) return e;
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_dev[device]);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + kScratchHist);
+  uint32_t* state = reinterpret_cast<uint32_t*>(base + kScratchState);
+  unsigned long long* cand = reinterpret_cast<unsigned long long*>(base + kScratchCand);
+  uint32_t* blk = reinterpret_cast<uint32_t*>(base + kScratchBlk);
+  const long nblk = (n + kTieBlock - 1) / kTieBlock;
+  hipLaunchKernelGGL(topk_reset_kernel, dim3(1), dim3(256), 0, s, hist, state, (uint32_t)k);
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(1024), dim3(256), 0, s, score, n, shift, hist, state);
+    hipLaunchKernelGGL(radix_pick_kernel, dim3(1), dim3(256), 0, s, shift, hist, state);
+  }
+  hipLaunchKernelGGL(gather_above_kernel, dim3((unsigned)nblk), dim3(256), 0, s, score, n, state, cand, blk);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(256), 0, s, blk, nblk);
+  hipLaunchKernelGGL(gather_ties_kernel, dim3((unsigned)nblk), dim3(256), 0, s, score, n, k, state, cand, blk);
+  long P = 1;
+  while (P < k) P <<= 1;
+  const size_t shm = (size_t)P * sizeof(unsigned long long);
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sort_out_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(sort_out_kernel, dim3(1), dim3(1024), shm, s, k, cand, idx);
+  return hipGetLastError();
 }
 
 hipError_t topk_select(const float* score, long n, long k, int64_t* idx, ScreenScratch& sc, hipStream_t s) {
