@@ -131,7 +131,7 @@ def copy_calibration(mib, reps=3):
     return {"bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}
 
 
-def surrogate_leg(ctx, rows, res, n_test=512, n_cand=1_000_000, k=10_000, epochs=100):
+def surrogate_leg(ctx, rows, res, n_test=512, n_cand=1_000_000, k=10_000, epochs=250):
     """Trains the MLP on the batch's own solver labels (switched flag, switching time and field
     after the timed window), reports the held-out switching-field error and times 1M-candidate
     screening rounds over the same design box."""
@@ -192,6 +192,55 @@ def surrogate_leg(ctx, rows, res, n_test=512, n_cand=1_000_000, k=10_000, epochs
             "valid_at_2pct": bool(head.size and head.mean() <= 0.02)}
 
 
+def thermal_leg(ctx, meshes, realizations=1024, steps=40, dt=5e-15, temperature=300.0):
+    """Thermal-erasure workload: each mesh (the patch island, one mesh seed per design) carries
+    `realizations` Philox streams of the single-island material in a static stray field drawn
+    uniformly in 0.3-0.6 T along -z, at 300 K, integrated with stochastic Heun in FP32 at dt for
+    `steps` steps.  Reports realization-ns/s, the FP32 matrix-core rate of the demag products
+    (2 N^2 R flops per field evaluation, two evaluations per step) divided by the whole step time
+    (exchange and field phases included; the GEMM kernel alone is in the profile) and the erased
+    fractions."""
+    import numpy as np
+    from paper_1603_09493_amd import bpm, roofline, thermal
+    from paper_1603_09493_amd import inputs as I
+    rng = np.random.default_rng(3)
+    mat = I.Material()
+    ctx.clear_instances()
+    ids, flops, B = [], 0.0, []
+    t0 = time.perf_counter()
+    for dsg, mesh in enumerate(meshes):
+        mid = ctx.mesh_add(mesh, keep=2)
+        B.append(float(rng.uniform(0.3, 0.6)))
+        fld = I.Field(kind=I.FIELD_UNIFORM, B_peak=B[-1], dir=(0.0, 0.0, -1.0), t_rise=0.0)
+        ids.append([ctx.instance_add(mid, mat, fld, seed=(3 << 48) | (dsg << 20) | r) for r in range(realizations)])
+        flops += 2 * 2.0 * mesh.n * mesh.n * realizations
+    setup_s = time.perf_counter() - t0
+    kw = dict(precision=32, integrator=bpm.HEUN, dt_fixed=dt, temperature=temperature)
+    ctx.run(t_end=2 * dt, **kw)        # warm-up: graph capture, first touch
+    ctx.sync()
+    t0 = time.perf_counter()
+    ctx.run(t_end=steps * dt, **kw)
+    ctx.sync()
+    wall = time.perf_counter() - t0
+    k_ms = ctx.last_run_info()["kernel_ms"]
+    erased = []
+    for grp in ids:
+        k, n_ok = thermal.count_erased(ctx.results(grp))
+        erased.append(k / realizations)
+    ctx.clear_instances()
+    tf = flops * steps / (k_ms * 1e-3) / 1e12
+    n_real = len(meshes) * realizations
+    return {"designs": len(meshes), "realizations_per_design": realizations,
+            "nodes_per_island_mean": float(np.mean([m.n for m in meshes])), "steps": steps, "dt_fs": dt * 1e15,
+            "temperature_K": temperature, "stray_field_T": [min(B), max(B)],
+            "value": n_real * steps * dt * 1e9 / wall, "unit": "realization-ns/s", "kernel_ms": k_ms,
+            "ms_per_heun_step": k_ms / steps, "setup_s": setup_s,
+            "demag_tflops_over_step_time": tf,
+            "demag_flops_per_step_over_step_time_frac_fp32_mfma": tf / roofline.MI355X_FP32_TFLOPS,
+            "erased_fraction_max": max(erased),
+            "exposure_ns": steps * dt * 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +256,9 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run three device copies of this many MiB (scales the profiler's byte counters)")
     ap.add_argument("--cpu-slice-ps", type=float, default=16.0, help="simulated time per oracle island (ps)")
+    ap.add_argument("--thermal", type=int, default=64,
+                    help="designs of the thermal-erasure leg (x 1024 realizations each; 0 = skip)")
+    ap.add_argument("--thermal-steps", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -221,6 +273,7 @@ def main():
     ins = I.design_inputs_many(rows)
     log(f"meshed {len(ins)} islands ({sum(m.n for m, _, _ in ins)} nodes, "
         f"{min(m.n for m, _, _ in ins)}-{max(m.n for m, _, _ in ins)} per island)")
+    thermal_meshes = I.patch_island_meshes([1 + d for d in range(args.thermal)]) if args.thermal > 0 else []
     from paper_1603_09493_amd import bpm, roofline
     ctx = bpm.Context(0)
     t0 = time.perf_counter()
@@ -314,7 +367,10 @@ def main():
         os._exit(0)
 
     signal.signal(signal.SIGTERM, on_term)
-    reserve = 25.0 + (0.0 if args.no_surrogate else 40.0) + (0.0 if args.no_cpu_baseline else 45.0)
+    # wall time kept for what follows the timed steps (measured: surrogate ~10 s, thermal leg
+    # ~3 s, oracle sample ~15 s), with margin
+    reserve = (20.0 + (0.0 if args.no_surrogate else 25.0) + (0.0 if args.no_cpu_baseline else 30.0)
+               + (0.0 if args.thermal <= 0 else 10.0 + 0.1 * args.thermal))
     stop = None
     t_step = None
     for k in range(args.steps):
@@ -347,6 +403,13 @@ def main():
                                                     if solver_rate else None)
         except Exception as e:   # the line is still printed
             out["surrogate"] = {"error": repr(e)}
+    if args.thermal > 0:
+        try:
+            out["thermal"] = thermal_leg(ctx, thermal_meshes, steps=args.thermal_steps)
+            log(f"thermal: {out['thermal']['value']:.3g} realization-ns/s, demag flops over step time "
+                f"{out['thermal']['demag_tflops_over_step_time']:.1f} TFLOP/s")
+        except Exception as e:
+            out["thermal"] = {"error": repr(e)}
     ctx.close()
     if not args.no_cpu_baseline:
         try:

@@ -265,7 +265,7 @@ def patch_workload(seed: int = 1, n_target: int = 2000, sigma_rel: float = 0.05)
 
     Returns (mesh, [Material]*9, [Field]*9, offsets[9][3]).
     """
-    mesh = island_mesh_target(9 * NM, 2.25 * NM, 3 * NM, 7 * NM, n_target, seed=seed)
+    mesh = patch_island_mesh(seed, n_target)
     rng = np.random.default_rng(seed)
     base = Material()
     mats, flds, offs = [], [], []
@@ -363,26 +363,42 @@ def _design_inputs_job(args):
     return design_inputs(x, seed)
 
 
-def design_inputs_many(X: np.ndarray, seeds=None, workers: int = 0):
-    """design_inputs for every row of X (mesh seed = row index unless seeds is given), meshed by a
-    pool of worker processes (workers = 0: up to 16, bounded by the CPUs this process may use).
-    Call it before any GPU work in the process: the workers are started with 'spawn'."""
+def _pool_map(fn, jobs, workers: int = 0, chunksize: int = 16):
+    """[fn(j) for j in jobs] on a pool of worker processes started with 'spawn' (workers = 0: up to
+    16, bounded by the CPUs this process may use); serial for short lists.  Call it before any GPU
+    work in the process."""
     import concurrent.futures as cf
     import multiprocessing as mp
     import os
-    X = np.asarray(X, dtype=np.float64)
-    seeds = list(range(X.shape[0])) if seeds is None else list(seeds)
-    jobs = [(X[q], int(seeds[q])) for q in range(X.shape[0])]
     if workers <= 0:
         try:
             avail = len(os.sched_getaffinity(0))
         except AttributeError:
             avail = os.cpu_count() or 1
         workers = max(1, min(16, avail))
-    if workers == 1 or len(jobs) < 32:
-        return [_design_inputs_job(j) for j in jobs]
+    if workers == 1 or len(jobs) < 8:
+        return [fn(j) for j in jobs]
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        return list(ex.map(_design_inputs_job, jobs, chunksize=16))
+        return list(ex.map(fn, jobs, chunksize=max(1, min(chunksize, len(jobs) // workers))))
+
+
+def design_inputs_many(X: np.ndarray, seeds=None, workers: int = 0):
+    """design_inputs for every row of X (mesh seed = row index unless seeds is given), meshed by a
+    pool of worker processes.  Call it before any GPU work in the process."""
+    X = np.asarray(X, dtype=np.float64)
+    seeds = list(range(X.shape[0])) if seeds is None else list(seeds)
+    return _pool_map(_design_inputs_job, [(X[q], int(seeds[q])) for q in range(X.shape[0])], workers)
+
+
+def patch_island_mesh(seed: int, n_target: int = 2000) -> Mesh:
+    """The island of the 3x3 patch (elliptic 18 x 4.5 nm, soft 3 nm on hard 7 nm) with mesh seed
+    `seed`."""
+    return island_mesh_target(9 * NM, 2.25 * NM, 3 * NM, 7 * NM, n_target, seed=seed)
+
+
+def patch_island_meshes(seeds, workers: int = 0):
+    """patch_island_mesh for every seed, on a pool of worker processes (before any GPU work)."""
+    return _pool_map(patch_island_mesh, [int(s) for s in seeds], workers, chunksize=2)
 
 
 def random_unit_m(n: int, seed: int, cone: float = math.pi) -> np.ndarray:

@@ -188,3 +188,39 @@ def test_boltzmann_equilibrium_many_realizations(ctx):
     assert abs((mz ** 2 - ref[None, :]).mean()) < 0.01
     # both wells populated (barrier crossings happened): the sign of m_z is balanced
     assert abs(np.sign(mz).mean()) < 0.1
+
+
+def _reversed_fraction_boltzmann(s, h):
+    """Macrospin in a uniaxial well (barrier parameter s = K V / kB T) with a field along -z
+    (h = Ms V B / kB T): P(m_z < 0) with the Boltzmann density exp(s x^2 - h x) in x = cos(theta)
+    (sin(theta) d(theta) = dx)."""
+    w = lambda x: math.exp(s * x * x - h * x)
+    return quad(w, -1, 0)[0] / quad(w, -1, 1)[0]
+
+
+def test_erasure_fraction_matches_boltzmann(ctx):
+    """Thermally induced erasure (stochastic LLG, Heun, FP32): 4096 realizations of a small
+    rigid island (exchange and interlayer coupling far stiffer than kB T, no demag) from +z in a
+    static field along -z at 300 K, barrier about 3 kB T.  After about ten relaxation times the
+    erased fraction (hard-layer <m_z> < 0) matches the Boltzmann reversed fraction of the
+    macrospin within four standard errors."""
+    from paper_1603_09493_amd import bpm, thermal
+    mesh = I.island_mesh(1.5e-9, 1.5e-9, 1e-9, 1e-9, 1.0e-9, seed=4)
+    Ms, Temp, R = 1.0e6, 300.0, 4096
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh, np.zeros((mesh.n, mesh.n)), keep=2)
+    V = ctx.mesh_get_assembly(mid)["V"].sum()
+    K = 3.0 * KB * Temp / V              # s = 3
+    B = 0.5 * KB * Temp / (Ms * V)       # h = 0.5
+    mat = I.Material(Ms=(Ms, Ms), K=(K, K), A=(200e-12, 200e-12), A_int=200e-12, alpha=1.0)
+    _case("heun-erasure", n=mesh.n, R=R, K=f"{K:.3g}", B=f"{B:.4f}")
+    er = thermal.run_erasure(ctx, mesh, mat, B, R, t_end=0.6e-9, dt=1.5e-15, temperature=Temp,
+                             key_base=(11 << 32), mesh_id=mid)
+    p_ref = _reversed_fraction_boltzmann(3.0, 0.5)
+    z = (er.p - p_ref) / math.sqrt(p_ref * (1 - p_ref) / R)
+    print(f"[heun-erasure] erased {er.k}/{er.n} = {er.p:.4f}, Boltzmann {p_ref:.4f}, z = {z:.2f}, "
+          f"label {er.label:.3f}, {er.wall_s:.1f} s", flush=True)
+    assert er.status_ok == R
+    assert 0.5 < p_ref < 0.9
+    assert abs(z) < 4.0, z
+    assert abs(er.label - thermal.logit_label(er.k, er.n)) == 0.0

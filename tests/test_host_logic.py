@@ -72,3 +72,13 @@ def test_mesher_renumbering_is_a_relabelling_with_smaller_spread():
     assert np.all(det > 0)
     s0, s1 = _spread(m0), _spread(m1)
     assert s1.max() < 0.8 * s0.max() and s1.mean() < 0.8 * s0.mean(), (s0.max(), s1.max(), s0.mean(), s1.mean())
+
+
+def test_erasure_label_and_count():
+    import math
+    from paper_1603_09493_amd import thermal
+    assert abs(thermal.logit_label(0, 1024) - math.log(0.5 / 1024.5)) < 1e-12
+    assert abs(thermal.logit_label(1024, 1024) + thermal.logit_label(0, 1024)) < 1e-12
+    assert abs(thermal.logit_label(512, 1024)) < 1e-12
+    res = [dict(status=0, mz_hard=-0.2), dict(status=0, mz_hard=0.9), dict(status=-5, mz_hard=-1.0)]
+    assert thermal.count_erased(res) == (1, 2)
