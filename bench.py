@@ -278,8 +278,11 @@ def main():
     ctx = bpm.Context(0)
     t0 = time.perf_counter()
     ids, sizes, nnzs = [], [], []
+    # the batch keeps its operators as FP32 packed upper-triangle tiles only (about half the bytes
+    # of row-major S); --full-demag keeps the row-major FP32 copy for the full product
+    keep = bpm.KEEP_S32 if args.full_demag else bpm.KEEP_S32_TILES
     for q, (mesh, mat, fld) in enumerate(ins):
-        mid = ctx.mesh_add(mesh, keep=2)
+        mid = ctx.mesh_add(mesh, keep=keep)
         ids.append(ctx.instance_add(mid, mat, fld))
         sizes.append(mesh.n)
         nnzs.append(int(ctx.mesh_get_assembly(mid, pattern_only=True)))
@@ -291,6 +294,15 @@ def main():
     sl = args.slice_ps * 1e-12
     kw = dict(precision=32, rtol=1e-5)
 
+    # launch shape tuned on the batch itself: one 256-thread workgroup per island (two islands per
+    # compute unit) or one 512-thread workgroup per island
+    t0 = time.perf_counter()
+    cands = [1, -1]
+    tuned, tune_ms = ctx.autotune(cands, probe_attempts=12, t_end=sl, precision=32, rtol=1e-5, flags=flags)
+    tune_info = {"candidates": ["256 threads x 1 wg/island", "512 threads x 1 wg/island"],
+                 "ms_per_attempt": [float(x) for x in tune_ms], "chosen": int(tuned),
+                 "tune_s": time.perf_counter() - t0}
+    log(f"autotune: {dict(zip(tune_info['candidates'], [round(x, 2) for x in tune_info['ms_per_attempt']]))}")
     for w in range(args.warmup):
         ctx.run(t_end=sl / 10, flags=flags, **kw)
         ctx.sync()
@@ -335,13 +347,14 @@ def main():
                 "simulated_ns": sim_ns,
                 "slice_ps": args.slice_ps,
                 "steps_requested": args.steps,
-                "demag_product": "full S" if args.full_demag else "upper triangle of S (64x64 tiles)",
+                "demag_product": "full S" if args.full_demag else "upper triangle of S, packed 64x64 tiles",
                 "switched_fraction": float(np.mean([r["switched"] for r in res])) if res else None,
                 "attempts_mean": float(att.mean()), "attempts_max": int(att.max()),
                 "status_ok": int(sum(r["status"] == 0 for r in res)) if res else 0,
                 "setup_s": setup_s,
                 "grid": ctx.last_run_info()["grid"],
                 "threads_per_wg": ctx.last_run_layout()["threads"],
+                "autotune": tune_info,
             },
             "roofline": {
                 "bound": "hbm",

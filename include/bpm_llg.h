@@ -48,8 +48,10 @@ enum { BPM_DP45 = 0, BPM_DP5_FIXED = 1, BPM_HEUN = 2 };
 
 typedef struct bpm_ctx bpm_ctx;
 
-/* Creates a context on HIP device `device`.  *out receives the handle. */
-int bpm_create(bpm_ctx** out, int device);
+/* Creates a context on HIP device `device`.  *out receives the handle.  tune_cache (nullable):
+ * path of the launch-shape cache that bpm_autotune appends to and this call reads (NULL: the
+ * environment variable BPM_TUNE_CACHE, if set; an empty string: no cache file). */
+int bpm_create(bpm_ctx** out, int device, const char* tune_cache);
 void bpm_destroy(bpm_ctx* ctx);
 const char* bpm_last_error(const bpm_ctx* ctx);
 
@@ -81,15 +83,22 @@ typedef struct {
 int bpm_mesh_add(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, double demag_beta,
                  int32_t* mesh_id);
 
-/* As bpm_mesh_add, choosing which device copies of S to keep (flags: BPM_KEEP_S64 and/or
- * BPM_KEEP_S32).  A group without the FP64 copy cannot run at precision 64 (and vice versa);
- * large batches of FP32 runs keep only the FP32 copy to halve the footprint. */
-enum { BPM_KEEP_S64 = 1, BPM_KEEP_S32 = 2 };
+/* As bpm_mesh_add, choosing which device copies of S to keep (flags, any combination):
+ *   BPM_KEEP_S64        row-major FP64 [n][ldS] (precision-64 runs);
+ *   BPM_KEEP_S32        row-major FP32 [n][ldS] (precision-32 runs of every kind);
+ *   BPM_KEEP_S32_TILES  FP32 upper triangle only, packed in 64 x 64 tiles: about half the bytes
+ *                       of the row-major copy; read by the upper-triangle product of FP32 runs
+ *                       with BPM_FLAG_SYMMETRIC_DEMAG and one workgroup per group (it is used for
+ *                       them whenever kept).
+ * A run needs a copy it can use (BPM_EINVAL otherwise): a group keeping only the packed tiles
+ * runs only in such launches (not in BPM_HEUN runs or cooperative launches); large batches of
+ * FP32 runs keep only the packed tiles. */
+enum { BPM_KEEP_S64 = 1, BPM_KEEP_S32 = 2, BPM_KEEP_S32_TILES = 4 };
 int bpm_mesh_add_ex(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, double demag_beta,
                     int32_t flags, int32_t* mesh_id);
 
 /* Copies the group's demag operator to host memory S_out [n][n] (FP64, or the widened FP32 copy
- * if only that is kept). */
+ * if only that is kept, or both triangles unpacked from the packed tiles). */
 int bpm_mesh_get_S(bpm_ctx* ctx, int32_t mesh_id, double* S_out);
 
 /* Copies the host-assembled quantities of a group: V [n], rowptr [n+1], col [nnz], K [nnz],
@@ -190,13 +199,14 @@ int bpm_run(bpm_ctx* ctx, const bpm_run_opts* opts, void* hip_stream);
 /* Waits for the run; returns the first ABI-level error of the run. */
 int bpm_sync(bpm_ctx* ctx);
 
-/* Autotuner of the launch shape: runs the current instances (one mesh group) for probe_attempts
- * step attempts with each candidate number of workgroups per group cand[0..n_cand) (a negative
- * candidate -g means g workgroups of 512 threads instead of 256), times the
- * stepping kernel with HIP events and keeps the fastest in *best.  ms_per_attempt (may be NULL)
+/* Autotuner of the launch shape: runs the current instances (one or many mesh groups) for
+ * probe_attempts step attempts with each candidate number of workgroups per group
+ * cand[0..n_cand) (a negative candidate -g means g workgroups of 512 threads instead of 256; for
+ * batches of many islands, 1 = one 256-thread workgroup per island, two islands per compute unit,
+ * and -1 = one 512-thread workgroup per island), times the stepping kernel with HIP events (per
+ * attempt of the longest-running system) and keeps the fastest in *best.  ms_per_attempt (may be NULL)
  * receives the time per attempt of each candidate (INFINITY where a candidate cannot run).  The
- * choice is cached in the context (and appended to the file named by the environment variable
- * BPM_TUNE_CACHE, read at bpm_create) under (size bucket of N, instance count, precision), and
+ * choice is cached in the context (and appended to the tune_cache file of bpm_create) under (size bucket of N, instance count, precision), and
  * bpm_run uses it when wg_per_group is 0.  Results of the probe runs are discarded. */
 int bpm_autotune(bpm_ctx* ctx, const bpm_run_opts* opts, int32_t n_cand, const int32_t* cand,
                  int64_t probe_attempts, int32_t* best, double* ms_per_attempt);
@@ -216,8 +226,10 @@ int bpm_get_results(bpm_ctx* ctx, int32_t n, const int32_t* ids, bpm_result* out
 /* Trajectory samples [cap][9] = (t, <mx>, <my>, <mz> (moment weighted), <mz>_soft, <mz>_hard
  * (volume weighted), |B_app(centroid)|, dt, err). */
 int bpm_get_trajectory(bpm_ctx* ctx, int32_t id, double* out, int64_t cap, int64_t* n_written);
-/* Final magnetisation of an instance, host [3][n] FP64. */
-int bpm_get_m(bpm_ctx* ctx, int32_t id, double* m_out);
+/* Final magnetisation of an instance as FP64 [3][n] (the unit vectors of its nodes), into host
+ * memory (dst_is_device = 0) or device memory (dst_is_device != 0; written by a kernel on the
+ * context's stream, complete when the call returns). */
+int bpm_get_m(bpm_ctx* ctx, int32_t id, void* dst, int32_t dst_is_device);
 /* Wall time of the last run's kernels (ms, HIP events on the run stream) and launch data. */
 int bpm_last_run_info(bpm_ctx* ctx, double* kernel_ms, int32_t* grid, int32_t* wg_per_group);
 /* Launch layout of the last DP5 run (any pointer may be NULL): threads per workgroup, rows of S

@@ -24,6 +24,7 @@ FLAG_WG512 = 2
 FLAG_STREAM_S = 4
 FLAG_WG256 = 8
 FLAG_CONTINUE = 16
+KEEP_S64, KEEP_S32, KEEP_S32_TILES = 1, 2, 4
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
 
@@ -101,7 +102,7 @@ def lib():
         pass
     L = C.CDLL(LIB_PATH)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
-    L.bpm_create.argtypes = [C.POINTER(P), C.c_int]
+    L.bpm_create.argtypes = [C.POINTER(P), C.c_int, C.c_char_p]
     L.bpm_destroy.argtypes = [P]
     L.bpm_destroy.restype = None
     L.bpm_last_error.argtypes = [P]
@@ -119,7 +120,7 @@ def lib():
     L.bpm_autotune.argtypes = [P, C.POINTER(bpm_run_opts), I32, P, I64, C.POINTER(I32), P]
     L.bpm_get_results.argtypes = [P, I32, P, P]
     L.bpm_get_trajectory.argtypes = [P, I32, P, I64, C.POINTER(I64)]
-    L.bpm_get_m.argtypes = [P, I32, P]
+    L.bpm_get_m.argtypes = [P, I32, P, I32]
     L.bpm_last_run_info.argtypes = [P, C.POINTER(D), C.POINTER(I32), C.POINTER(I32)]
     L.bpm_last_run_layout.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]
     L.bpm_mlp_num_params.argtypes = []
@@ -169,10 +170,10 @@ def field_struct(f) -> bpm_field:
 class Context:
     """One bpm_ctx on a HIP device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache=None):
         self.L = lib()
         self.h = C.c_void_p()
-        rc = self.L.bpm_create(C.byref(self.h), int(device))
+        rc = self.L.bpm_create(C.byref(self.h), int(device), None if tune_cache is None else tune_cache.encode())
         if rc != 0:
             raise BpmError(rc, "bpm_create failed (no HIP device?)")
         self.mesh_n = {}
@@ -195,7 +196,8 @@ class Context:
 
     # meshes -------------------------------------------------------------------------------------
     def mesh_add(self, mesh, S=None, beta=0.0, keep=3) -> int:
-        """keep: 1 = FP64 demag operator only, 2 = FP32 only, 3 = both."""
+        """keep (bits): 1 = row-major FP64 demag operator, 2 = row-major FP32, 4 = FP32 upper-triangle
+        packed tiles (for the upper-triangle product of FP32 batches)."""
         xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
         tet = np.ascontiguousarray(mesh.tet, dtype=np.int32)
         layer = np.ascontiguousarray(mesh.layer, dtype=np.int32)
@@ -258,10 +260,10 @@ class Context:
         self._check(self.L.bpm_run(self.h, C.byref(o), None if stream is None else C.c_void_p(stream)))
 
     def autotune(self, candidates, probe_attempts=60, t_end=1e-9, precision=32, integrator=DP45, rtol=1e-5,
-                 dt0=1e-15, dt_fixed=0.0):
+                 dt0=1e-15, dt_fixed=0.0, flags=0):
         o = bpm_run_opts()
         o.precision, o.integrator, o.t_end, o.dt0, o.dt_fixed = precision, integrator, t_end, dt0, dt_fixed
-        o.rtol, o.atol, o.dt_min = rtol, rtol, 1e-19
+        o.rtol, o.atol, o.dt_min, o.flags = rtol, rtol, 1e-19, flags
         cand = np.ascontiguousarray(candidates, dtype=np.int32)
         ms = np.empty(len(cand))
         best = C.c_int32()
@@ -284,10 +286,15 @@ class Context:
         self._check(self.L.bpm_get_trajectory(self.h, iid, _p(out), cap, C.byref(nw)))
         return out[:nw.value]
 
-    def get_m(self, iid, n):
-        out = np.empty((3, n))
-        self._check(self.L.bpm_get_m(self.h, iid, _p(out)))
-        return out
+    def get_m(self, iid, n, out=None):
+        """Final magnetisation [3][n] FP64: into a new host array, or into `out` (a device tensor
+        of 3n doubles)."""
+        if out is not None:
+            self._check(self.L.bpm_get_m(self.h, iid, _dp(out), 1))
+            return out
+        host = np.empty((3, n))
+        self._check(self.L.bpm_get_m(self.h, iid, _p(host), 0))
+        return host
 
     def last_run_info(self):
         ms = C.c_double(); grid = C.c_int32(); G = C.c_int32()

@@ -23,6 +23,9 @@ namespace bpm {
 std::string hip_err_string(hipError_t e) { return hipGetErrorString(e); }
 
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream);
+void pack_tiles_device(int n, int ldS, const double* S, float* T, hipStream_t stream);
+hipError_t extract_m_device(int precision, long n, long rstride, long offset, const void* src, double* dst,
+                            hipStream_t stream);
 void symmetrize_device(int n, int ldS, double* S, hipStream_t stream);
 
 template <typename real>
@@ -120,6 +123,10 @@ struct bpm_ctx {
   int run_nmax = 0, run_ng = 0;
   double *run_d_err = nullptr, *run_d_obs = nullptr, *run_d_mom = nullptr;
   unsigned long long* run_d_bar = nullptr;
+  int2* run_d_map = nullptr;                 // blockIdx -> (group, local workgroup)
+  std::vector<int> run_group_G, run_group_n, run_group_sys0, run_group_nsys;
+  std::vector<int64_t> run_att_start;       // attempts of each system when the last launch began
+  std::vector<int2> run_wmap;               // host copy of a reordered map (kept until the copy ran)
   // autotuned workgroups per mesh group, keyed by (log2 bucket of N, instances, precision)
   std::map<std::tuple<int, int, int>, int> tune;
   std::string tune_path;
@@ -144,7 +151,7 @@ static int fail(bpm_ctx* c, int code, const std::string& msg) {
 
 extern "C" {
 
-int bpm_create(bpm_ctx** out, int device) {
+int bpm_create(bpm_ctx** out, int device, const char* tune_cache) {
   if (!out) return BPM_EINVAL;
   *out = nullptr;
   int count = 0;
@@ -160,7 +167,9 @@ int bpm_create(bpm_ctx** out, int device) {
   // device address of this GPU's scratch area of the allocation-free top-k (a failure here is
   // retried, and reported, by bpm_topk_noalloc)
   (void)topk_scratch_init(device);
-  if (const char* p = std::getenv("BPM_TUNE_CACHE")) {
+  const char* cache = tune_cache ? tune_cache : std::getenv("BPM_TUNE_CACHE");
+  if (cache && *cache) {
+    const char* p = cache;
     c->tune_path = p;
     std::ifstream f(p);
     int b, r, pr, g;
@@ -178,6 +187,7 @@ void bpm_destroy(bpm_ctx* c) {
   for (auto& m : c->meshes) {
     if (m->dS64) hipFree(m->dS64);
     if (m->dS32) hipFree(m->dS32);
+    if (m->dS32t) hipFree(m->dS32t);
   }
   c->mesh_arena.clear();
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
@@ -244,7 +254,8 @@ int bpm_mesh_add(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double 
 
 int bpm_mesh_add_ex(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double demag_beta, int32_t flags,
                     int32_t* mesh_id) {
-  if (c && !(flags & (BPM_KEEP_S64 | BPM_KEEP_S32))) return fail(c, BPM_EINVAL, "bpm_mesh_add_ex: keep at least one precision of S");
+  if (c && !(flags & (BPM_KEEP_S64 | BPM_KEEP_S32 | BPM_KEEP_S32_TILES)))
+    return fail(c, BPM_EINVAL, "bpm_mesh_add_ex: keep at least one copy of S");
   if (!c) return BPM_EINVAL;
   if (!mesh || !mesh_id || !mesh->xyz || !mesh->tet || !mesh->node_layer)
     return fail(c, BPM_EINVAL, "bpm_mesh_add: null argument");
@@ -291,6 +302,10 @@ int bpm_mesh_add_ex(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, doub
     HIPCHK(c, hipMalloc(&g->dS32, sizeof(float) * (size_t)n * ldS));
     to_float_device((size_t)n * ldS, g->dS64, g->dS32, c->own_stream);
   }
+  if (flags & BPM_KEEP_S32_TILES) {
+    HIPCHK(c, hipMalloc(&g->dS32t, sizeof(float) * (size_t)tile_count(n) * kTile * kTile));
+    pack_tiles_device(n, ldS, g->dS64, g->dS32t, c->own_stream);
+  }
   HIPCHK(c, hipStreamSynchronize(c->own_stream));
   if (!(flags & BPM_KEEP_S64)) {
     HIPCHK(c, hipFree(g->dS64));
@@ -312,6 +327,17 @@ int bpm_mesh_get_S(bpm_ctx* c, int32_t id, double* S_out) {
   if (g.dS64) {
     HIPCHK(c, hipMemcpy2D(S_out, sizeof(double) * g.n, g.dS64, sizeof(double) * ldS, sizeof(double) * g.n, g.n,
                           hipMemcpyDeviceToHost));
+  } else if (!g.dS32) {
+    // only the packed FP32 tiles: unpack both triangles
+    const int nb = (g.n + kTile - 1) / kTile;
+    std::vector<float> tmp((size_t)tile_count(g.n) * kTile * kTile);
+    HIPCHK(c, hipMemcpy(tmp.data(), g.dS32t, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < g.n; ++k)
+      for (int l = 0; l < g.n; ++l) {
+        const int a = std::min(k, l), b = std::max(k, l);
+        const size_t f = (size_t)tile_index(nb, a / kTile, b / kTile);
+        S_out[(size_t)k * g.n + l] = tmp[f * kTile * kTile + tile_offset(a % kTile, b % kTile)];
+      }
   } else {
     std::vector<float> tmp((size_t)g.n * ldS);
     HIPCHK(c, hipMemcpy(tmp.data(), g.dS32, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost));
@@ -433,6 +459,14 @@ int bpm_clear_instances(bpm_ctx* c) {
 
 }  // extern "C"
 
+// Relative cost of one field evaluation of an n-node island in a batch: the bytes of its demag
+// tiles plus a per-node term for the gather-bound exchange and field phases (on the 4096-island
+// batch those phases take about 0.43 of the demag stream's time, i.e. about 1.2 KB of stream per
+// node).
+static double island_eval_cost(int n) {
+  return (double)tile_count(n) * kTile * kTile * sizeof(float) + 1200.0 * n;
+}
+
 template <typename real>
 static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   Arena& A = c->run;
@@ -501,14 +535,14 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   }
   const bool sym = (o->flags & BPM_FLAG_SYMMETRIC_DEMAG) && sizeof(real) == 4;
   int tuned_wg = 0;
-  if (o->wg_per_group <= 0 && ng == 1) {
+  if (o->wg_per_group <= 0) {
     auto it = c->tune.find(tune_key(nmax, ninst, (int)sizeof(real) * 8));
     if (it != c->tune.end()) tuned_wg = it->second;
   }
-  // 512-thread workgroups: when asked for, when the tuner chose them, and by default for launches
-  // of several mesh groups (twice the waves per island; measured 26 % faster on a batch of 4096
-  // uneven islands); BPM_FLAG_WG256 forces 256
-  const bool want512 = (o->flags & BPM_FLAG_WG512) || tuned_wg < 0 || (ng > 1 && o->wg_per_group <= 0);
+  // 512-thread workgroups: when asked for, when the tuner chose them, and by default for untuned
+  // launches of several mesh groups (twice the waves per island); BPM_FLAG_WG256 forces 256
+  const bool want512 = (o->flags & BPM_FLAG_WG512) || tuned_wg < 0 ||
+                       (ng > 1 && o->wg_per_group <= 0 && tuned_wg == 0);
   const int bs = (want512 && !(o->flags & BPM_FLAG_WG256)) ? 512 : 256;
   const size_t lds_budget = sym ? 48 * 1024 : 96 * 1024;
   int RB = (int)std::max<size_t>(1, std::min<size_t>(16, lds_budget / (sizeof(real) * (size_t)ldS_max)));
@@ -635,7 +669,12 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     v.inst0 = c->group_inst0[mi]; v.sys0 = group_sys0[gi];
     v.rowptr = d.rowptr; v.col = d.col; v.colx = d.colx; v.K = d.K; v.D = d.D; v.DT = d.DT;
     v.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
-    if (!v.S) return fail(c, BPM_EINVAL, "bpm_run: a mesh group does not keep S in the run precision");
+    v.St = std::is_same<real, float>::value ? g.dS32t : nullptr;
+    // the packed tiles serve only the upper-triangle product of single-workgroup groups
+    if (!v.S && !(v.St && sym && G[gi] == 1 && !coop))
+      return fail(c, BPM_EINVAL, v.St ? "bpm_run: a group keeping only the packed tiles of S needs "
+                                        "BPM_FLAG_SYMMETRIC_DEMAG and one workgroup per group"
+                                      : "bpm_run: a mesh group does not keep S in the run precision");
     v.V = d.V; v.layer = d.layer; v.partner = d.partner; v.aif = d.aif;
     v.x = d.x; v.y = d.y; v.z = d.z;
     for (int k = 0; k < 3; ++k) v.cen[k] = g.centroid[k];
@@ -662,14 +701,23 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     wg += G[gi];
   }
   // Workgroups are dispatched in map order and, past the resident capacity, start as earlier ones
-  // finish: the groups with the most demag work per workgroup (N^2 R / G) go first, so that the
-  // long islands do not start last and set the length of the launch.
+  // finish: the groups with the most work per workgroup go first, so that long islands do not
+  // start last and set the length of the launch.  Work of a group = its demag bytes per evaluation
+  // (N^2 R / G) times the evaluations it will need, which the exchange-limited step makes
+  // proportional to the largest exchange field scale 2 A / Ms over its layers and instances.
   {
+    std::vector<double> cost(ng);
+    for (int gi = 0; gi < ng; ++gi) {
+      double stiff = 0.0;
+      for (int r = 0; r < gv[gi].R; ++r) {
+        const InstConst& k = ic[gv[gi].inst0 + r];
+        stiff = std::max({stiff, k.cex[0], k.cex[1]});
+      }
+      cost[gi] = island_eval_cost(gv[gi].n) * gv[gi].R / G[gi] * stiff;
+    }
     std::vector<int> order(ng);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      return (double)gv[a].n * gv[a].n * gv[a].R / G[a] > (double)gv[b].n * gv[b].n * gv[b].R / G[b];
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     for (int gi : order) {
       gv[gi].wg0 = (int)wmap.size();
       for (int w = 0; w < G[gi]; ++w) wmap.push_back(make_int2(gi, w));
@@ -731,6 +779,13 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   c->run_d_obs = d_obs;
   c->run_d_mom = d_mom;
   c->run_d_bar = d_bar;
+  c->run_d_map = d_map;
+  c->run_group_G = G;
+  c->run_group_n.resize(ng);
+  c->run_group_sys0 = group_sys0;
+  c->run_group_nsys = group_nsys;
+  for (int gi = 0; gi < ng; ++gi) c->run_group_n[gi] = gv[gi].n;
+  c->run_att_start.assign(nsys, 0);
   return BPM_OK;
 }
 
@@ -751,6 +806,32 @@ static int resume_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
   HIPCHK(c, hipMemsetAsync(c->run_d_obs, 0, sizeof(double) * c->run_ninst * 18, stream));
   HIPCHK(c, hipMemsetAsync(c->run_d_mom, 0, sizeof(double) * c->run_ninst * 9, stream));
   HIPCHK(c, hipMemsetAsync(c->run_d_bar, 0, sizeof(unsigned long long) * c->run_ng, stream));
+  // Single-workgroup groups are dispatched by the work they took in the previous launch (its
+  // attempts times their demag bytes), largest first: step counts differ by several times between
+  // islands, and the longest ones must not start last.
+  const int ng = (int)c->run_group_n.size();
+  bool all_single = true;
+  for (int gi = 0; gi < ng; ++gi) all_single = all_single && c->run_group_G[gi] == 1;
+  if (all_single && (int)c->h_sys_out.size() == c->run_nsys) {
+    std::vector<double> cost(ng, 0.0);
+    std::vector<int64_t> att_now(c->run_nsys);
+    for (int sl = 0; sl < c->run_nsys; ++sl) att_now[sl] = c->h_sys_out[sl].n_accept + c->h_sys_out[sl].n_reject;
+    for (int gi = 0; gi < ng; ++gi) {
+      int64_t att = 0;
+      for (int sl = c->run_group_sys0[gi]; sl < c->run_group_sys0[gi] + c->run_group_nsys[gi]; ++sl) {
+        const bool live = c->h_sys_out[sl].status == BPM_OK && c->h_sys_out[sl].t_reached < o->t_end;
+        if (live) att = std::max<int64_t>(att, std::max<int64_t>(1, att_now[sl] - c->run_att_start[sl]));
+      }
+      cost[gi] = island_eval_cost(c->run_group_n[gi]) * (double)att;
+    }
+    std::vector<int> order(ng);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    c->run_wmap.resize(ng);
+    for (int q = 0; q < ng; ++q) c->run_wmap[q] = make_int2(order[q], 0);
+    HIPCHK(c, hipMemcpyAsync(c->run_d_map, c->run_wmap.data(), sizeof(int2) * ng, hipMemcpyHostToDevice, stream));
+    c->run_att_start = att_now;
+  }
   const GroupView<real>* d_groups = reinterpret_cast<const GroupView<real>*>(c->run_d_groups);
   HIPCHK(c, hipEventRecord(c->ev0, stream));
   {
@@ -808,7 +889,7 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
     h.n = g.n; h.R = R; h.ldS = (g.n + 15) / 16 * 16; h.inst0 = (int)ic.size(); h.ldR = (R + 3) / 4 * 4;
     h.rowptr = d.rowptr; h.col = d.col; h.colx = d.colx; h.K = d.K; h.D = d.D; h.DT = d.DT;
     h.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
-    if (!h.S) return fail(c, BPM_EINVAL, "bpm_run: a mesh group does not keep S in the run precision");
+    if (!h.S) return fail(c, BPM_EINVAL, "bpm_run: BPM_HEUN needs the row-major S in the run precision (BPM_KEEP_S64 / BPM_KEEP_S32)");
     h.V = d.V; h.layer = d.layer; h.partner = d.partner; h.aif = d.aif; h.x = d.x; h.y = d.y;
     h.Vsoft = g.vol_layer[0]; h.Vhard = g.vol_layer[1];
     const size_t cs = (size_t)g.n * R;
@@ -1010,14 +1091,7 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
   if (o->integrator == BPM_HEUN) return fail(c, BPM_EINVAL, "bpm_autotune: tunes the DP5 kernels only");
   if (c->insts.empty()) return fail(c, BPM_ESTATE, "bpm_autotune: no instances");
   int nmax = 1;
-  std::vector<int> meshes;
-  for (auto& I : c->insts) {
-    nmax = std::max(nmax, c->meshes[I.mesh]->n);
-    meshes.push_back(I.mesh);
-  }
-  std::sort(meshes.begin(), meshes.end());
-  meshes.erase(std::unique(meshes.begin(), meshes.end()), meshes.end());
-  if (meshes.size() != 1) return fail(c, BPM_EINVAL, "bpm_autotune: tunes runs of one mesh group");
+  for (auto& I : c->insts) nmax = std::max(nmax, c->meshes[I.mesh]->n);
   double best_t = INFINITY;
   int best_g = 0;
   for (int q = 0; q < n_cand; ++q) {
@@ -1030,8 +1104,9 @@ int bpm_autotune(bpm_ctx* c, const bpm_run_opts* o, int32_t n_cand, const int32_
     if (rc == BPM_OK) rc = bpm_sync(c);
     double t = INFINITY;
     if (rc == BPM_OK) {
-      const SysOut& so = c->h_sys_out[0];
-      const int64_t att = std::max<int64_t>(1, so.n_accept + so.n_reject);
+      // time per attempt of the longest-running system (every system gets the same budget)
+      int64_t att = 1;
+      for (const SysOut& so : c->h_sys_out) att = std::max<int64_t>(att, so.n_accept + so.n_reject);
       t = c->kernel_ms / (double)att;
     } else if (rc != BPM_EINVAL) {
       return rc;
@@ -1150,37 +1225,40 @@ int bpm_get_trajectory(bpm_ctx* c, int32_t id, double* out, int64_t cap, int64_t
   return BPM_OK;
 }
 
-int bpm_get_m(bpm_ctx* c, int32_t id, double* m_out) {
+int bpm_get_m(bpm_ctx* c, int32_t id, void* dst, int32_t dst_is_device) {
   if (!c) return BPM_EINVAL;
-  if (!m_out) return fail(c, BPM_EINVAL, "bpm_get_m: null output");
+  if (!dst) return fail(c, BPM_EINVAL, "bpm_get_m: null output");
   if (!c->have_results) return fail(c, BPM_ESTATE, "bpm_get_m: no synchronised run");
   if (id < 0 || id >= (int)c->slot_of.size() || c->slot_of[id] < 0) return fail(c, BPM_EINVAL, "bpm_get_m: bad instance id");
+  HIPCHK(c, hipSetDevice(c->device));
   const int s = c->slot_of[id];
   const int mi = c->slot_group[s];
-  const int n = c->meshes[mi]->n;
-  if (c->run_rfast) {
-    const int R = c->slot_R[s], r = c->slot_local[s];
-    const size_t cnt = 3 * (size_t)n * R;
-    std::vector<double> all(cnt);
-    if (c->run_precision == 64) {
-      HIPCHK(c, hipMemcpy(all.data(), c->group_m[mi], sizeof(double) * cnt, hipMemcpyDeviceToHost));
-    } else {
-      std::vector<float> tmp(cnt);
-      HIPCHK(c, hipMemcpy(tmp.data(), c->group_m[mi], sizeof(float) * cnt, hipMemcpyDeviceToHost));
-      for (size_t q = 0; q < cnt; ++q) all[q] = tmp[q];
-    }
-    for (int comp = 0; comp < 3; ++comp)
-      for (int i = 0; i < n; ++i) m_out[(size_t)comp * n + i] = all[(size_t)comp * n * R + (size_t)i * R + r];
+  const long n = c->meshes[mi]->n;
+  // [3][n][R] for thermal runs, [R][3][n] for stepping runs
+  const long rstride = c->run_rfast ? c->slot_R[s] : 1;
+  const long offset = c->run_rfast ? c->slot_local[s] : (long)c->slot_local[s] * 3 * n;
+  if (dst_is_device) {
+    HIPCHK(c, extract_m_device(c->run_precision, n, rstride, offset, c->group_m[mi], static_cast<double*>(dst),
+                               c->own_stream));
+    HIPCHK(c, hipStreamSynchronize(c->own_stream));
     return BPM_OK;
   }
-  const size_t off = (size_t)c->slot_local[s] * 3 * n;
+  double* m_out = static_cast<double*>(dst);
+  const size_t cnt = c->run_rfast ? 3 * (size_t)n * rstride : 3 * (size_t)n;
+  const size_t first = c->run_rfast ? 0 : (size_t)offset;
+  std::vector<double> all(cnt);
   if (c->run_precision == 64) {
-    HIPCHK(c, hipMemcpy(m_out, reinterpret_cast<double*>(c->group_m[mi]) + off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(all.data(), reinterpret_cast<double*>(c->group_m[mi]) + first, sizeof(double) * cnt,
+                        hipMemcpyDeviceToHost));
   } else {
-    std::vector<float> tmp(3 * (size_t)n);
-    HIPCHK(c, hipMemcpy(tmp.data(), reinterpret_cast<float*>(c->group_m[mi]) + off, sizeof(float) * 3 * n, hipMemcpyDeviceToHost));
-    for (size_t q = 0; q < tmp.size(); ++q) m_out[q] = tmp[q];
+    std::vector<float> tmp(cnt);
+    HIPCHK(c, hipMemcpy(tmp.data(), reinterpret_cast<float*>(c->group_m[mi]) + first, sizeof(float) * cnt,
+                        hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < cnt; ++q) all[q] = tmp[q];
   }
+  for (long comp = 0; comp < 3; ++comp)
+    for (long i = 0; i < n; ++i)
+      m_out[comp * n + i] = c->run_rfast ? all[(size_t)(comp * n + i) * rstride + offset] : all[(size_t)(comp * n + i)];
   return BPM_OK;
 }
 

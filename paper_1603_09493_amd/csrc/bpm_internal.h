@@ -33,6 +33,23 @@ __device__ __forceinline__ const GLB T* glb(const T* p) { return (const GLB T*)p
 
 constexpr int kCsrPad = 8;   // zero CSR entries stored past the last row of every device mesh
 
+// Packed upper-triangle tiles of the FP32 demag operator: the NB (NB + 1) / 2 tiles of 64 x 64
+// with I <= J (NB = ceil(n / 64)), in row-major order of (I, J), 4096 floats each, zero beyond n.
+// Inside a tile, element (r, c) with r = 16 rg + t and c = 4 cq + q sits at
+// ((4 t + rg) * 16 + cq) * 4 + q: the sixteen 16-byte words a lane (rg, cq) of a wave reads are
+// one word of each of sixteen contiguous 1 KB blocks, one block per load instruction of the wave.
+constexpr int kTile = 64;
+__host__ __device__ inline long tile_count(int n) {
+  const long nb = (n + kTile - 1) / kTile;
+  return nb * (nb + 1) / 2;
+}
+__host__ __device__ inline long tile_index(int nb, int I, int J) {   // I <= J
+  return (long)I * nb - (long)I * (I - 1) / 2 + (J - I);
+}
+__host__ __device__ inline int tile_offset(int r, int c) {
+  return (((r & 15) * 4 + (r >> 4)) * 16 + (c >> 2)) * 4 + (c & 3);
+}
+
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kMu0 = 4.0e-7 * kPi;          // T m / A
 constexpr double kGammaE = 1.76085963023e11;   // rad / (s T)
@@ -59,6 +76,7 @@ struct MeshGroup {
   // device copies
   double* dS64 = nullptr;                 // [n][n]
   float* dS32 = nullptr;
+  float* dS32t = nullptr;                 // FP32 upper-triangle 64x64 tiles, packed (see kTile)
   bool S_ready = false;
 };
 
@@ -120,7 +138,8 @@ struct GroupView {
   const real* K;
   const real* D;              // [nnz][3]
   const real* DT;             // [nnz][3]
-  const real* S;              // [n][n]
+  const real* S;              // [n][ldS] row-major (may be null when St is given)
+  const float* St;            // FP32 packed upper-triangle tiles (null if not kept)
   const real* V;
   const int32_t* layer;
   const int32_t* partner;

@@ -73,6 +73,52 @@ __global__ void to_float_kernel(size_t cnt, const double* __restrict__ a, float*
     b[i] = (float)a[i];
 }
 
+// magnetisation of one instance as FP64 [3][n]: from [R][3][n] (stepping runs, rstride = 1,
+// offset = r 3 n) or from [3][n][R] (thermal runs, rstride = R, offset = r)
+template <typename real>
+__global__ void extract_m_kernel(long n, long rstride, long offset, const real* __restrict__ src,
+                                 double* __restrict__ dst) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  const long comp = i / n, node = i - comp * n;
+  dst[i] = (double)src[offset + (comp * n + node) * rstride];
+}
+
+hipError_t extract_m_device(int precision, long n, long rstride, long offset, const void* src, double* dst,
+                            hipStream_t stream) {
+  const unsigned blocks = (unsigned)((3 * n + 255) / 256);
+  if (precision == 64)
+    hipLaunchKernelGGL(extract_m_kernel<double>, dim3(blocks), dim3(256), 0, stream, n, rstride, offset,
+                       static_cast<const double*>(src), dst);
+  else
+    hipLaunchKernelGGL(extract_m_kernel<float>, dim3(blocks), dim3(256), 0, stream, n, rstride, offset,
+                       static_cast<const float*>(src), dst);
+  return hipGetLastError();
+}
+
+// FP32 packed upper-triangle tiles of S (layout: bpm_internal.h, kTile); one workgroup per tile
+__global__ void pack_tiles_kernel(int n, int ldS, int nb, const double* __restrict__ S, float* __restrict__ T) {
+  const long f = blockIdx.x;
+  int I = 0;
+  long rem = f;
+  while (rem >= nb - I) {
+    rem -= nb - I;
+    ++I;
+  }
+  const int J = I + (int)rem;
+  float* tile = T + f * (long)(kTile * kTile);
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int r = e / kTile, c = e - r * kTile;
+    const int row = I * kTile + r, col = J * kTile + c;
+    tile[tile_offset(r, c)] = (row < n && col < n) ? (float)S[(size_t)row * ldS + col] : 0.0f;
+  }
+}
+
+void pack_tiles_device(int n, int ldS, const double* S, float* T, hipStream_t stream) {
+  const int nb = (n + kTile - 1) / kTile;
+  hipLaunchKernelGGL(pack_tiles_kernel, dim3((unsigned)tile_count(n)), dim3(256), 0, stream, n, ldS, nb, S, T);
+}
+
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream) {
   hipLaunchKernelGGL(to_float_kernel, dim3(1024), dim3(256), 0, stream, cnt, a, b);
 }

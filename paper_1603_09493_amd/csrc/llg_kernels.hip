@@ -479,7 +479,8 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
 // by halving exchanges, so that each lane ends with one row (64I + lane) and one column
 // (64J + 4cq + rg), which it adds into u in LDS (uL, RB x ldS after bL).  The order of those LDS
 // additions, and with it the rounding of u, varies from run to run.  Tiles go round-robin over
-// the waves of the workgroup.
+// the waves of the workgroup.  The tiles come from the packed copy when the group keeps it (each
+// load instruction of a wave then reads one contiguous kilobyte), else from the row-major S.
 template <typename real, int BS>
 __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, real* bL, int RB) {
   static_assert(sizeof(real) == 4, "the tiled symmetric product is the FP32 path");
@@ -488,6 +489,7 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
   constexpr int nw = BS / 64;
   const int rg = lane >> 4, cq = lane & 15;
   const GLB float* Sg = reinterpret_cast<const GLB float*>(glb(g.S));
+  const GLB float* Stg = g.St ? glb(g.St) : nullptr;      // packed tiles, when the group keeps them
   GLB float* __restrict__ ug = reinterpret_cast<GLB float*>(glb(g.u));
   const int NB = (n + 63) >> 6;
   const int ntile = NB * (NB + 1) / 2;
@@ -513,10 +515,17 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
       const int col0 = 64 * J + 4 * cq;
       const bool cok = col0 < ldS;   // ldS is a multiple of 4: the whole 16-byte word is in the row
       float4 sv[16];
+      if (Stg) {
+        // packed tile: load t of the wave reads the contiguous kilobyte t (zero beyond n)
+        const GLB float4* tile = reinterpret_cast<const GLB float4*>(Stg + (size_t)f * (kTile * kTile));
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int row = row0 + t;
-        sv[t] = (cok && row < n) ? *reinterpret_cast<const GLB float4*>(Sg + (size_t)row * ldS + col0) : z4;
+        for (int t = 0; t < 16; ++t) sv[t] = tile[(t * 4 + rg) * 16 + cq];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const int row = row0 + t;
+          sv[t] = (cok && row < n) ? *reinterpret_cast<const GLB float4*>(Sg + (size_t)row * ldS + col0) : z4;
+        }
       }
 #pragma unroll 1
       for (int r = 0; r < rn; ++r) {
@@ -1276,7 +1285,7 @@ __device__ __forceinline__ void dp5_entry(const GroupView<real>* __restrict__ gr
 }
 
 template <typename real, bool kFixed, int BS, bool kL, bool kX>
-__global__ __launch_bounds__(BS) void dp5_kernel(const GroupView<real>* __restrict__ groups,
+__global__ __launch_bounds__(BS, 2) void dp5_kernel(const GroupView<real>* __restrict__ groups,
                                                  RunParams P, int RB, LdsPlan LP) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Ctl c;
@@ -1325,12 +1334,23 @@ __global__ __launch_bounds__(256) void energy_kernel(const GroupView<real>* __re
     e_loc += -ic.Ms[L] * Vi * (mi[0] * bx + mi[1] * by + mi[2] * bz);
   }
   __syncthreads();
-  // demag: (mu0/2) b^T S b
+  // demag: (mu0/2) b^T S b (S entries from the row-major copy, else from the packed tiles)
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nb = (n + kTile - 1) / kTile;
   double ed = 0.0;
   for (int k = wid; k < n; k += 256 / 64) {
     double acc = 0.0;
-    for (int l = lane; l < n; l += 64) acc += (double)g.S[(size_t)k * g.ldS + l] * bL[l];
+    for (int l = lane; l < n; l += 64) {
+      double skl;
+      if (g.S) {
+        skl = (double)g.S[(size_t)k * g.ldS + l];
+      } else {
+        const int a = min(k, l), b = max(k, l);
+        skl = (double)g.St[(size_t)tile_index(nb, a / kTile, b / kTile) * (kTile * kTile) +
+                           tile_offset(a % kTile, b % kTile)];
+      }
+      acc += skl * bL[l];
+    }
     acc = wave_sum(acc);
     if (lane == 0) ed += 0.5 * kMu0 * bL[k] * acc;
   }

@@ -49,10 +49,14 @@ def _batch_rows():
     return X, rows
 
 
-def test_tiled_symmetric_product_against_oracle(ctx, oracle_mod):
+@pytest.mark.parametrize("keep", [3, 6, 4])
+def test_tiled_symmetric_product_against_oracle(ctx, oracle_mod, keep):
     """FP32 fixed-step DP5 (200 steps of 5 fs) of four batch islands in one launch, one workgroup
     each, upper-triangle demag product, from seeded states within 0.6 rad of +z: every node within
-    1e-4 of the FP64 oracle, and within 2e-5 of the same launch with the full product."""
+    1e-4 of the FP64 oracle, and within 2e-5 of the same launch with the full product.  keep 3:
+    tiles read from the row-major S; 6: from the packed upper-triangle tiles; 4: the group keeps
+    only the packed tiles (the full product is then refused), whose unpacked copy equals S to FP32
+    rounding."""
     from paper_1603_09493_amd import bpm
     X, rows = _batch_rows()
     T, dt = 1e-12, 5e-15
@@ -62,23 +66,37 @@ def test_tiled_symmetric_product_against_oracle(ctx, oracle_mod):
         mesh, mat, fld = I.design_inputs(X[q], seed=q)
         om = oracle_mod.OracleMesh(mesh)
         S = om.demag_S()
-        mid = ctx.mesh_add(mesh, S)
+        mid = ctx.mesh_add(mesh, S, keep=keep)
+        if keep == 4:
+            Sg = ctx.mesh_get_S(mid)
+            assert np.array_equal(Sg, Sg.T)
+            assert np.abs(Sg - S).max() <= 2 ** -23 * np.abs(S).max(), np.abs(Sg - S).max()
         m0 = I.random_unit_m(mesh.n, seed=100 + q, cone=0.6)
         cases.append((mesh, mat, fld, om, S, ctx.instance_add(mid, mat, fld, m0=m0), m0))
-    _case("tiled-symmetric", sizes=[c[0].n for c in cases])
+    _case("tiled-symmetric", keep=keep, sizes=[c[0].n for c in cases])
     assert min(c[0].n for c in cases) < 300 and max(c[0].n for c in cases) > 2800
-    got = {}
+    got, energy = {}, {}
     for name, flags in (("sym", bpm.FLAG_SYMMETRIC_DEMAG), ("full", 0)):
+        if keep == 4 and name == "full":
+            with pytest.raises(bpm.BpmError) as e:
+                ctx.run(t_end=T, precision=32, integrator=bpm.DP5_FIXED, dt_fixed=dt, wg_per_group=1, flags=flags)
+            assert e.value.code == bpm.BPM_EINVAL
+            continue
         ctx.run(t_end=T, precision=32, integrator=bpm.DP5_FIXED, dt_fixed=dt, wg_per_group=1, flags=flags)
         ctx.sync()
         assert ctx.last_run_info()["wg_per_group"] == 1
         got[name] = [ctx.get_m(c[5], c[0].n) for c in cases]
-        assert all(r["status"] == 0 and r["n_accept"] == 200 for r in ctx.results([c[5] for c in cases]))
-    for (mesh, mat, fld, om, S, iid, m0), ms, mf in zip(cases, got["sym"], got["full"]):
+        res = ctx.results([c[5] for c in cases])
+        assert all(r["status"] == 0 and r["n_accept"] == 200 for r in res)
+        energy[name] = [r["energy"] for r in res]
+    for idx, (mesh, mat, fld, om, S, iid, m0) in enumerate(cases):
+        ms = got["sym"][idx]
         mo, ro, _ = om.run(S, [mat], [fld], dict(t_end=T, integrator=oracle_mod.DP5_FIXED, dt_fixed=dt), m0=m0)
         assert np.abs(mo[0] - m0).max() > 1e-2          # the state moved
         assert np.abs(ms - mo[0]).max() <= 1e-4, (mesh.n, np.abs(ms - mo[0]).max())
-        assert np.abs(ms - mf).max() <= 2e-5, (mesh.n, np.abs(ms - mf).max())
+        assert abs(energy["sym"][idx] / ro[0]["energy"] - 1) <= 1e-3, (energy["sym"][idx], ro[0]["energy"])
+        if "full" in got:
+            assert np.abs(ms - got["full"][idx]).max() <= 2e-5, (mesh.n, np.abs(ms - got["full"][idx]).max())
 
 
 def test_continued_fixed_step_run_is_identical(ctx, oracle_mod):
@@ -172,7 +190,7 @@ def test_continue_misuse_is_rejected(ctx):
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="tests/golden/cfg2_switching.json not generated")
 def test_batch_switching_parity_64_designs():
     """64 designs of the batch (266-2898 nodes) in one FP32 adaptive launch, one workgroup per
-    island, upper-triangle demag product, 0.3 ns: the switched flag agrees with the FP64 oracle
+    island, upper-triangle demag product on the packed tiles (the bench's storage), 0.3 ns: the switched flag agrees with the FP64 oracle
     wherever the oracle's final hard-layer <m_z> is clear of zero, and the switching time and
     field agree within 1 %."""
     from paper_1603_09493_amd import bpm
@@ -185,7 +203,7 @@ def test_batch_switching_parity_64_designs():
         for d in gold["designs"]:
             mesh, mat, fld = I.design_inputs(X[d["row"]], seed=d["row"])
             assert mesh.n == d["n"]
-            ids.append(c.instance_add(c.mesh_add(mesh, keep=2), mat, fld))
+            ids.append(c.instance_add(c.mesh_add(mesh, keep=bpm.KEEP_S32_TILES), mat, fld))
         _case("batch-64", sizes=f"{min(d['n'] for d in gold['designs'])}-{max(d['n'] for d in gold['designs'])}")
         # one workgroup per island, as in the 4096-island launch (64 groups alone would get a
         # cooperative share of the GPU each)
@@ -205,3 +223,68 @@ def test_batch_switching_parity_64_designs():
             assert abs(r["t_sw"] / d["t_sw"] - 1) <= 0.01, (d, r["t_sw"])
             assert abs(r["B_sw"] / d["B_sw"] - 1) <= 0.01, (d, r["B_sw"])
     assert n_sw >= 16
+
+
+def test_batch_autotune_and_tune_cache(tmp_path):
+    """The launch-shape tuner on a batch of islands: one 256-thread workgroup per island (two
+    islands per compute unit) or one 512-thread workgroup; it keeps the faster, a run that names
+    no shape uses it, and a new context given the same cache file uses it without tuning."""
+    from paper_1603_09493_amd import bpm
+    X = I.sample_designs(48, seed=2)
+    cache = str(tmp_path / "tune.txt")
+
+    def setup(c):
+        ids = []
+        for q, x in enumerate(X):
+            mesh, mat, fld = I.design_inputs(x, seed=q)
+            ids.append(c.instance_add(c.mesh_add(mesh, keep=2), mat, fld))
+        return ids
+
+    c = bpm.Context(0, tune_cache=cache)
+    try:
+        ids = setup(c)
+        _case("batch-autotune", islands=len(ids))
+        best, ms = c.autotune([1, -1], probe_attempts=12, t_end=1e-11, precision=32, rtol=1e-5,
+                              flags=bpm.FLAG_SYMMETRIC_DEMAG)
+        assert np.all(np.isfinite(ms)) and best == [1, -1][int(np.argmin(ms))], (best, ms)
+        c.run(t_end=1e-13, precision=32, rtol=1e-5, flags=bpm.FLAG_SYMMETRIC_DEMAG)
+        c.sync()
+        assert c.last_run_info()["wg_per_group"] == 1
+        assert c.last_run_layout()["threads"] == (512 if best < 0 else 256)
+        assert all(r["status"] == 0 for r in c.results(ids))
+    finally:
+        c.close()
+    line = open(cache).read().split()
+    assert len(line) == 4 and int(line[3]) == best
+    c2 = bpm.Context(0, tune_cache=cache)
+    try:
+        setup(c2)
+        c2.run(t_end=1e-13, precision=32, rtol=1e-5, flags=bpm.FLAG_SYMMETRIC_DEMAG)
+        c2.sync()
+        assert c2.last_run_layout()["threads"] == (512 if best < 0 else 256)
+    finally:
+        c2.close()
+
+
+@pytest.mark.parametrize("precision,integrator", [(64, 1), (32, 0), (32, 2)])
+def test_get_m_into_device_memory(ctx, precision, integrator):
+    """bpm_get_m into a device buffer equals the host copy, for both state layouts (stepping runs
+    [R][3][n], thermal runs [3][n][R]) and both precisions."""
+    import torch
+    from paper_1603_09493_amd import bpm
+    mesh, mat, fld = I.single_island_workload(n_target=300)
+    ctx.clear_instances()
+    mid = ctx.mesh_add(mesh)
+    ids = [ctx.instance_add(mid, mat, fld, m0=I.random_unit_m(mesh.n, 40 + r, cone=0.5), seed=r) for r in range(3)]
+    _case("get-m-device", precision=precision, integrator=integrator)
+    kw = dict(t_end=0.2e-12, precision=precision, integrator=integrator)
+    if integrator != 0:
+        kw.update(dt_fixed=2e-15, temperature=300.0 if integrator == 2 else 0.0)
+    ctx.run(**kw)
+    ctx.sync()
+    for i in ids:
+        host = ctx.get_m(i, mesh.n)
+        dev = torch.empty(3 * mesh.n, dtype=torch.float64, device="cuda")
+        ctx.get_m(i, mesh.n, out=dev)
+        assert np.array_equal(dev.cpu().numpy().reshape(3, mesh.n), host)
+        assert np.abs(np.sqrt((host ** 2).sum(0)) - 1).max() < 1e-5
