@@ -43,7 +43,7 @@ enum {
   BPM_EMAXSTEPS = -7         /* per instance: max_steps attempts used up */
 };
 
-enum { BPM_FIELD_UNIFORM = 0, BPM_FIELD_POLE = 1 };
+enum { BPM_FIELD_UNIFORM = 0, BPM_FIELD_POLE = 1, BPM_FIELD_GRID = 2 };
 enum { BPM_DP45 = 0, BPM_DP5_FIXED = 1, BPM_HEUN = 2 };
 
 typedef struct bpm_ctx bpm_ctx;
@@ -127,10 +127,19 @@ typedef struct {
  *       fx = (1 - tanh(sx / L_grad)) / 2,  sx = x - x_off[0] - v[0] t
  *       fy = (tanh((sy + W_pole/2)/L_grad) - tanh((sy - W_pole/2)/L_grad)) / 2,
  *            sy = y - x_off[1] - v[1] t.
+ *   BPM_FIELD_GRID:    f = the trilinear interpolation, at s = x - x_off - v t, of a grid of field
+ *     vectors (the paper samples the precomputed head field on a 2.5 nm grid and hands it to the
+ *     recording simulation, Sec. II.A): grid is host [3][nz][ny][nx] FP32 in tesla (component,
+ *     then z, y, x), node (i, j, k) at g_origin + g_h (i, j, k), nx, ny, nz >= 2, g_h > 0; f = 0
+ *     outside the box the nodes span; dir is not used.  The grid is copied at
+ *     bpm_instance_add (instances given equal grids share one device copy).
  * Positions x are mesh coordinates plus the instance offset.                                 */
 typedef struct {
   int32_t kind, pad_;
   double B_peak, dir[3], t_rise, v[3], x_off[3], L_grad, W_pole, B_ext[3];
+  const float* grid;          /* BPM_FIELD_GRID only (else may be NULL) */
+  int32_t nx, ny, nz, pad2_;
+  double g_origin[3], g_h;
 } bpm_field;
 
 /* Adds an instance on mesh group mesh_id.  offset (may be NULL = 0) translates the island;

@@ -36,7 +36,7 @@
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_ENONFINITE = -5, OR_ESTEPUNDERFLOW = -6,
        OR_EMAXSTEPS = -7 };
 enum { OR_DP45 = 0, OR_DP5_FIXED = 1, OR_HEUN = 2 };
-enum { OR_FIELD_UNIFORM = 0, OR_FIELD_POLE = 1 };
+enum { OR_FIELD_UNIFORM = 0, OR_FIELD_POLE = 1, OR_FIELD_GRID = 2 };
 
 /* ------------------------------------------------------------------------------------------ */
 /* Public structs (mirrored by ctypes in oracle.py)                                            */
@@ -49,6 +49,9 @@ typedef struct {
 typedef struct {
   int32_t kind, pad_;
   double B_peak, dir[3], t_rise, v[3], x_off[3], L_grad, W_pole, B_ext[3];
+  const float *grid;           /* OR_FIELD_GRID: [3][nz][ny][nx] tesla */
+  int32_t nx, ny, nz, pad2_;
+  double g_origin[3], g_h;
 } or_field;
 
 typedef struct {
@@ -359,16 +362,46 @@ static double rise(const or_field *F, double t) {
   return r < 1.0 ? r : 1.0;
 }
 
-static void applied_B(const or_field *F, double t, double x, double y, double *B) {
+/* Field grid (the precomputed head field handed to the recording simulation, Sec. II.A):
+ * trilinear interpolation of the node vectors at the field-frame point s; zero outside the box
+ * spanned by the nodes.  Node (i, j, k) sits at g_origin + g_h (i, j, k). */
+static void grid_field(const or_field *F, const double *s, double *G) {
+  const int n[3] = {F->nx, F->ny, F->nz};
+  int lo[3];
+  double f[3];
+  G[0] = G[1] = G[2] = 0.0;
+  for (int a = 0; a < 3; a++) {
+    double u = (s[a] - F->g_origin[a]) / F->g_h;
+    if (u < 0.0 || u > (double)(n[a] - 1)) return;
+    int i = (int)floor(u);
+    if (i > n[a] - 2) i = n[a] - 2;
+    lo[a] = i;
+    f[a] = u - i;
+  }
+  size_t per_comp = (size_t)n[0] * n[1] * n[2];
+  for (int corner = 0; corner < 8; corner++) {
+    int ix = lo[0] + (corner & 1), iy = lo[1] + ((corner >> 1) & 1), iz = lo[2] + ((corner >> 2) & 1);
+    double w = ((corner & 1) ? f[0] : 1.0 - f[0]) * (((corner >> 1) & 1) ? f[1] : 1.0 - f[1]) *
+               (((corner >> 2) & 1) ? f[2] : 1.0 - f[2]);
+    size_t node = ((size_t)iz * n[1] + iy) * n[0] + ix;
+    for (int c = 0; c < 3; c++) G[c] += w * (double)F->grid[c * per_comp + node];
+  }
+}
+
+static void applied_B(const or_field *F, double t, double x, double y, double z, double *B) {
   double amp = F->B_peak * rise(F, t);
+  double dir[3] = {F->dir[0], F->dir[1], F->dir[2]};
   if (F->kind == OR_FIELD_POLE) {
     double sx = x - F->x_off[0] - F->v[0] * t;
     double sy = y - F->x_off[1] - F->v[1] * t;
     double fx = 0.5 * (1.0 - tanh(sx / F->L_grad));
     double fy = 0.5 * (tanh((sy + 0.5 * F->W_pole) / F->L_grad) - tanh((sy - 0.5 * F->W_pole) / F->L_grad));
     amp *= fx * fy;
+  } else if (F->kind == OR_FIELD_GRID) {
+    double sp[3] = {x - F->x_off[0] - F->v[0] * t, y - F->x_off[1] - F->v[1] * t, z - F->x_off[2] - F->v[2] * t};
+    grid_field(F, sp, dir);
   }
-  for (int c = 0; c < 3; c++) B[c] = amp * F->dir[c] + F->B_ext[c];
+  for (int c = 0; c < 3; c++) B[c] = amp * dir[c] + F->B_ext[c];
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -440,7 +473,7 @@ static void field_terms(const or_mesh *M, const double *S, const or_material *ma
       bint[0] = cint * mx[j]; bint[1] = cint * my[j]; bint[2] = cint * mz[j];
     }
     for (int c = 0; c < 3; c++) bd[c] = -OR_MU0 / Vi * Dtu[c * n + i];
-    applied_B(F, t, M->x[i] + off[0], M->y[i] + off[1], bz);
+    applied_B(F, t, M->x[i] + off[0], M->y[i] + off[1], M->z[i] + off[2], bz);
     for (int c = 0; c < 3; c++) {
       double bdip = Bdip ? Bdip[c] : 0.0;
       Btot[c * n + i] = bex[c] + ban[c] + bint[c] + bd[c] + bz[c] + bdip;
@@ -669,7 +702,8 @@ static void save_traj(or_system *Y, const double *y, double t, double dt, double
     if (!traj || ntraj[r] >= cap) continue;
     double obs[5], B[3];
     observe(Y->M, &Y->mat[r], y + (size_t)r * 3 * n, obs);
-    applied_B(&Y->fld[r], t, Y->M->centroid[0] + Y->off[3 * r], Y->M->centroid[1] + Y->off[3 * r + 1], B);
+    applied_B(&Y->fld[r], t, Y->M->centroid[0] + Y->off[3 * r], Y->M->centroid[1] + Y->off[3 * r + 1],
+              Y->M->centroid[2] + Y->off[3 * r + 2], B);
     double *s = traj + ((size_t)r * cap + ntraj[r]) * 9;
     s[0] = t; s[1] = obs[0]; s[2] = obs[1]; s[3] = obs[2]; s[4] = obs[3]; s[5] = obs[4];
     s[6] = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]); s[7] = dt; s[8] = err;
@@ -713,7 +747,8 @@ static void finalize_results(or_system *Y, const double *y, double t, or_cross *
     res[r].t_sw = cr[r].crossed ? cr[r].t_sw : NAN;
     if (cr[r].crossed) {
       double B[3];
-      applied_B(&Y->fld[r], cr[r].t_sw, Y->M->centroid[0] + Y->off[3 * r], Y->M->centroid[1] + Y->off[3 * r + 1], B);
+      applied_B(&Y->fld[r], cr[r].t_sw, Y->M->centroid[0] + Y->off[3 * r], Y->M->centroid[1] + Y->off[3 * r + 1],
+                Y->M->centroid[2] + Y->off[3 * r + 2], B);
       res[r].B_sw = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
     } else {
       res[r].B_sw = NAN;

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 DP45, DP5_FIXED, HEUN = 0, 1, 2
+FIELD_UNIFORM, FIELD_POLE, FIELD_GRID = 0, 1, 2
 OK, EINVAL, ENOMEM, ENONFINITE, ESTEPUNDERFLOW, EMAXSTEPS = 0, -1, -2, -5, -6, -7
 
 # Smear factor of the Gaussian charge blobs of the demag operator (std = beta * V_tet^(1/3)):
@@ -35,7 +36,8 @@ class Field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("B_peak", C.c_double),
                 ("dir", C.c_double * 3), ("t_rise", C.c_double), ("v", C.c_double * 3),
                 ("x_off", C.c_double * 3), ("L_grad", C.c_double), ("W_pole", C.c_double),
-                ("B_ext", C.c_double * 3)]
+                ("B_ext", C.c_double * 3), ("grid", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32), ("pad2_", C.c_int32), ("g_origin", C.c_double * 3), ("g_h", C.c_double)]
 
 
 class Opts(C.Structure):
@@ -108,12 +110,25 @@ def material(m) -> Material:
     return s
 
 
+_GRIDS = []   # float32 copies of field grids handed to the oracle (kept alive for its calls)
+
+
 def field(f) -> Field:
     s = Field()
     s.kind = f.kind
     s.B_peak, s.t_rise, s.L_grad, s.W_pole = f.B_peak, f.t_rise, f.L_grad, f.W_pole
     for c in range(3):
         s.dir[c], s.v[c], s.x_off[c], s.B_ext[c] = f.dir[c], f.v[c], f.x_off[c], f.B_ext[c]
+    grid = getattr(f, "grid", None)
+    if grid is not None:
+        g = np.ascontiguousarray(grid, dtype=np.float32)
+        _GRIDS.append(g)
+        del _GRIDS[:-64]
+        s.grid = g.ctypes.data
+        s.nz, s.ny, s.nx = (int(v) for v in g.shape[1:])
+        s.g_h = f.g_h
+        for c in range(3):
+            s.g_origin[c] = f.g_origin[c]
     return s
 
 

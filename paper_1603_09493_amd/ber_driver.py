@@ -9,6 +9,12 @@ BER_targ = 1/2 [1 - erf(H_crit / sqrt(2 sigma^2))].  If the head cannot switch t
 without H_ext the evaluation is aborted with BER = 1 (Fig. 1).
 
 Here the 12 simulations of a level are 12 instances of one batched launch (one mesh group).
+The target and the previous bit are the islands of the pseudo-hexagonal layout at their own
+positions under the same moving head field (inputs.recording_layout / recording_field); H_ext
+points along the head field at the island's centre, taken where that field is strongest during
+the write period (for a uniform or pole field: its `dir`).  Evaluation is sequential with early
+abort (Sec. II.C): a head that cannot write the target, or that rewrites the previous bit even
+without H_ext, gives BER_tot = 1 and the later error rates are not computed.
 The paper states the critical field was always inside {0..4 sigma}, yet its shingled designs of
 Table III imply about 5.4 and 6.0 sigma through Eq. (1); the first level therefore spans
 {0, sigma/2, ..., 5.5 sigma} and is extended while every field still switches.
@@ -21,6 +27,7 @@ import math
 import numpy as np
 
 from . import bpm
+from . import inputs as I
 
 
 def sigma_T(K_hard: float, Ms_hard: float) -> float:
@@ -43,37 +50,79 @@ class Search:
     aborted: bool
 
 
-def _level(ctx, mid, mat, fld, fields, t_end, precision, previous):
-    """One level: 12 instances with H_ext along -dir (target) or +dir (previous bit)."""
+def _trilinear(grid, origin, h, p):
+    """Trilinear sample of a [3][nz][ny][nx] grid at point p (zero outside the grid)."""
+    nz, ny, nx = grid.shape[1:]
+    u = (np.asarray(p, dtype=np.float64) - np.asarray(origin, dtype=np.float64)) / h
+    n = np.array([nx, ny, nz])
+    if np.any(u < 0.0) or np.any(u > n - 1):
+        return np.zeros(3)
+    i = np.minimum(np.floor(u).astype(int), n - 2)
+    f = u - i
+    out = np.zeros(3)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                w = (f[0] if dx else 1 - f[0]) * (f[1] if dy else 1 - f[1]) * (f[2] if dz else 1 - f[2])
+                out += w * grid[:, i[2] + dz, i[1] + dy, i[0] + dx]
+    return out
+
+
+def head_direction(fld, centre, t_end: float, samples: int = 128) -> np.ndarray:
+    """Unit vector of the head field (without B_ext) at `centre`, where its magnitude peaks over
+    [0, t_end]; the field's `dir` for the uniform and pole kinds."""
+    if fld.kind != I.FIELD_GRID:
+        d = np.asarray(fld.dir, dtype=np.float64)
+        return d / np.linalg.norm(d)
+    best, bn = None, -1.0
+    c = np.asarray(centre, dtype=np.float64)
+    for t in np.linspace(0.0, t_end, samples):
+        s = c - np.asarray(fld.x_off) - np.asarray(fld.v) * t
+        b = _trilinear(fld.grid, fld.g_origin, fld.g_h, s)
+        nb = float(np.linalg.norm(b))
+        if nb > bn:
+            best, bn = b, nb
+    if bn <= 0.0:
+        raise ValueError("the head field is zero at the island along its whole path")
+    return best / bn
+
+
+def _level(ctx, mid, mat, fld, fields, t_end, precision, previous, offset, hdir):
+    """One level: len(fields) instances with H_ext along -hdir (target) or +hdir (previous bit)."""
     ctx.clear_instances()
-    d = np.asarray(fld.dir, dtype=np.float64)
     sign = 1.0 if previous else -1.0
     ids = []
     for h in fields:
-        f = dataclasses.replace(fld, B_ext=tuple(sign * h * d))
-        ids.append(ctx.instance_add(mid, mat, f))
+        f = dataclasses.replace(fld, B_ext=tuple(np.asarray(fld.B_ext) + sign * h * hdir))
+        ids.append(ctx.instance_add(mid, mat, f, offset=offset))
     ctx.run(t_end=t_end, precision=precision, rtol=1e-5 if precision == 32 else 1e-6)
     ctx.sync()
     res = ctx.results(ids)
+    if any(r["status"] != 0 for r in res):
+        raise RuntimeError(f"recording simulation failed: statuses {[r['status'] for r in res]}")
     return np.array([bool(r["switched"]) for r in res])
 
 
 def critical_field(ctx: bpm.Context, mid: int, mat, fld, t_end: float = 1e-9, precision: int = 32,
-                   previous: bool = False, n_par: int = 12, refinements: int = 2, max_extend: int = 4) -> Search:
+                   previous: bool = False, n_par: int = 12, refinements: int = 2, max_extend: int = 4,
+                   offset=(0.0, 0.0, 0.0), centre=None) -> Search:
     """H_crit for the target bit (previous=False: switching must still happen) or for the
-    previous bit (previous=True: it must stay unswitched)."""
+    previous bit (previous=True: it must stay unswitched), the island placed at `offset`.
+    `centre` (default: offset) is where the H_ext direction is taken."""
     sig = sigma_T(mat.K[1], mat.Ms[1])
+    hdir = head_direction(fld, offset if centre is None else centre, t_end)
+    lev = lambda fs: _level(ctx, mid, mat, fld, fs, t_end, precision, previous, offset, hdir)
     want = (lambda sw: ~sw) if previous else (lambda sw: sw)   # True where writing succeeds
     fields = 0.5 * sig * np.arange(n_par)
     levels = []
-    ok = want(_level(ctx, mid, mat, fld, fields, t_end, precision, previous))
+    ok = want(lev(fields))
     levels.append((fields.copy(), ok.copy()))
     if not ok[0]:
         return Search(0.0, 0.0, 0.0, sig, 1.0, levels, True)
     ext = 0
     while ok.all() and ext < max_extend:
         fields = fields[-1] + 0.5 * sig * np.arange(1, n_par + 1)
-        ok = want(_level(ctx, mid, mat, fld, fields, t_end, precision, previous))
+        ok = want(lev(fields))
         levels.append((fields.copy(), ok.copy()))
         ext += 1
     if ok.all():
@@ -85,7 +134,7 @@ def critical_field(ctx: bpm.Context, mid: int, mat, fld, t_end: float = 1e-9, pr
     hi = float(fields[first_fail])
     for _ in range(refinements):
         fields = lo + (hi - lo) * np.arange(1, n_par + 1) / (n_par + 1)
-        ok = want(_level(ctx, mid, mat, fld, fields, t_end, precision, previous))
+        ok = want(lev(fields))
         levels.append((fields.copy(), ok.copy()))
         if ok.all():
             lo = float(fields[-1])
@@ -95,3 +144,38 @@ def critical_field(ctx: bpm.Context, mid: int, mat, fld, t_end: float = 1e-9, pr
             lo = float(fields[ff - 1]) if ff > 0 else lo
     h = 0.5 * (lo + hi)
     return Search(h, lo, hi, sig, ber_from_hcrit(h, sig), levels, False)
+
+
+@dataclasses.dataclass
+class WriteErrors:
+    ber_targ: float
+    ber_prev: float          # 1.0 when aborted at the target stage (not evaluated)
+    ber_tot: float           # BER_targ + BER_prev, + BER_adj when given; 1 on abort
+    stage: str               # "done", or the stage that aborted: "targ" / "prev"
+    targ: Search
+    prev: Search | None
+
+
+def write_errors(ctx: bpm.Context, mesh, mid: int, mat, fld, layout=None, t_end: float = I.BIT_PERIOD,
+                 precision: int = 32, ber_adj=None, **search) -> WriteErrors:
+    """BER_targ, then BER_prev (Eqs. (1)-(2)) for one design, with the early abort of Sec. II.C.
+
+    The target and the previous island (layout: inputs.recording_layout()) see the same moving
+    head field `fld` over one write period.  ber_adj, when given, is a callable returning BER_adj
+    (Eq. (3)); it is called only when both write stages passed."""
+    layout = I.recording_layout() if layout is None else layout
+    zc = 0.5 * (float(mesh.xyz[2].min()) + float(mesh.xyz[2].max()))
+    at = lambda p: (float(p[0]), float(p[1]), float(p[2]))
+    ctr = lambda p: (float(p[0]), float(p[1]), float(p[2]) + zc)
+    targ = critical_field(ctx, mid, mat, fld, t_end=t_end, precision=precision, previous=False,
+                          offset=at(layout["target"]), centre=ctr(layout["target"]), **search)
+    if targ.aborted:
+        return WriteErrors(1.0, 1.0, 1.0, "targ", targ, None)
+    prev = critical_field(ctx, mid, mat, fld, t_end=t_end, precision=precision, previous=True,
+                          offset=at(layout["previous"]), centre=ctr(layout["previous"]), **search)
+    if prev.aborted:
+        return WriteErrors(targ.ber, 1.0, 1.0, "prev", targ, prev)
+    tot = targ.ber + prev.ber
+    if ber_adj is not None:
+        tot += float(ber_adj())
+    return WriteErrors(targ.ber, prev.ber, min(1.0, tot), "done", targ, prev)

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbpmllg.so")
 
 BPM_OK, BPM_EINVAL, BPM_ENOMEM, BPM_EHIP, BPM_ESTATE = 0, -1, -2, -3, -4
 BPM_ENONFINITE, BPM_ESTEPUNDERFLOW, BPM_EMAXSTEPS = -5, -6, -7
-FIELD_UNIFORM, FIELD_POLE = 0, 1
+FIELD_UNIFORM, FIELD_POLE, FIELD_GRID = 0, 1, 2
 FLAG_SYMMETRIC_DEMAG = 1
 FLAG_WG512 = 2
 FLAG_STREAM_S = 4
@@ -48,7 +48,9 @@ class bpm_material(C.Structure):
 class bpm_field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("B_peak", C.c_double), ("dir", C.c_double * 3),
                 ("t_rise", C.c_double), ("v", C.c_double * 3), ("x_off", C.c_double * 3),
-                ("L_grad", C.c_double), ("W_pole", C.c_double), ("B_ext", C.c_double * 3)]
+                ("L_grad", C.c_double), ("W_pole", C.c_double), ("B_ext", C.c_double * 3),
+                ("grid", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad2_", C.c_int32),
+                ("g_origin", C.c_double * 3), ("g_h", C.c_double)]
 
 
 class bpm_run_opts(C.Structure):
@@ -164,6 +166,17 @@ def field_struct(f) -> bpm_field:
     s.B_peak, s.t_rise, s.L_grad, s.W_pole = f.B_peak, f.t_rise, f.L_grad, f.W_pole
     for c in range(3):
         s.dir[c], s.v[c], s.x_off[c], s.B_ext[c] = f.dir[c], f.v[c], f.x_off[c], f.B_ext[c]
+    grid = getattr(f, "grid", None)
+    if grid is not None:
+        g = np.ascontiguousarray(grid, dtype=np.float32)
+        if g.ndim != 4 or g.shape[0] != 3:
+            raise ValueError("field grid must be [3][nz][ny][nx]")
+        s._grid_keep = g                    # alive until the call that copies it returns
+        s.grid = g.ctypes.data
+        s.nz, s.ny, s.nx = (int(v) for v in g.shape[1:])
+        s.g_h = f.g_h
+        for c in range(3):
+            s.g_origin[c] = f.g_origin[c]
     return s
 
 

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "bpm_internal.h"
+#include "field_eval.h"
 #include "mlp_internal.h"
 #include "heun_internal.h"
 
@@ -127,6 +128,13 @@ struct bpm_ctx {
   std::vector<int> run_group_G, run_group_n, run_group_sys0, run_group_nsys;
   std::vector<int64_t> run_att_start;       // attempts of each system when the last launch began
   std::vector<int2> run_wmap;               // host copy of a reordered map (kept until the copy ran)
+  // field grids of BPM_FIELD_GRID instances, one device copy per distinct content
+  struct FieldGrid {
+    float* dev = nullptr;
+    std::shared_ptr<const std::vector<float>> host;
+    int32_t n[3] = {0, 0, 0};
+  };
+  std::map<uint64_t, FieldGrid> grids;
   // autotuned workgroups per mesh group, keyed by (log2 bucket of N, instances, precision)
   std::map<std::tuple<int, int, int>, int> tune;
   std::string tune_path;
@@ -190,6 +198,7 @@ void bpm_destroy(bpm_ctx* c) {
     if (m->dS32t) hipFree(m->dS32t);
   }
   c->mesh_arena.clear();
+  for (auto& kv : c->grids) hipFree(kv.second.dev);
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -366,7 +375,12 @@ int bpm_instance_add(bpm_ctx* c, int32_t mesh_id, const bpm_material* mat, const
   if (!c) return BPM_EINVAL;
   if (!mat || !f || !inst_id) return fail(c, BPM_EINVAL, "bpm_instance_add: null argument");
   if (mesh_id < 0 || mesh_id >= (int)c->meshes.size()) return fail(c, BPM_EINVAL, "bpm_instance_add: bad mesh id");
-  if (f->kind != BPM_FIELD_UNIFORM && f->kind != BPM_FIELD_POLE) return fail(c, BPM_EINVAL, "bpm_instance_add: bad field kind");
+  if (f->kind != BPM_FIELD_UNIFORM && f->kind != BPM_FIELD_POLE && f->kind != BPM_FIELD_GRID)
+    return fail(c, BPM_EINVAL, "bpm_instance_add: bad field kind");
+  if (f->kind == BPM_FIELD_GRID &&
+      (!f->grid || f->nx < 2 || f->ny < 2 || f->nz < 2 || !(f->g_h > 0.0) ||
+       (double)f->nx * f->ny * f->nz * 3 > 1.0e9))
+    return fail(c, BPM_EINVAL, "bpm_instance_add: a field grid needs data, nx, ny, nz >= 2 and g_h > 0");
   for (int L = 0; L < 2; ++L)
     if (!(mat->Ms[L] > 0.0)) return fail(c, BPM_EINVAL, "bpm_instance_add: Ms must be positive");
   if (!(mat->delta_int > 0.0) || !(mat->alpha >= 0.0)) return fail(c, BPM_EINVAL, "bpm_instance_add: delta_int > 0 and alpha >= 0 required");
@@ -403,6 +417,36 @@ int bpm_instance_add(bpm_ctx* c, int32_t mesh_id, const bpm_material* mat, const
   }
   k.key[0] = (uint32_t)seed;
   k.key[1] = (uint32_t)(seed >> 32);
+  k.grid = nullptr;
+  if (f->kind == BPM_FIELD_GRID) {
+    const size_t cnt = (size_t)3 * f->nx * f->ny * f->nz;
+    // FNV-1a over the dimensions and the bytes: instances given equal grids share one device copy
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&hsh](const void* p, size_t bytes) {
+      const unsigned char* b = static_cast<const unsigned char*>(p);
+      for (size_t q = 0; q < bytes; ++q) hsh = (hsh ^ b[q]) * 1099511628211ull;
+    };
+    const int32_t dims[3] = {f->nx, f->ny, f->nz};
+    mix(dims, sizeof(dims));
+    mix(f->grid, cnt * sizeof(float));
+    auto it = c->grids.find(hsh);
+    if (it == c->grids.end() || it->second.n[0] != f->nx || it->second.n[1] != f->ny || it->second.n[2] != f->nz ||
+        std::memcmp(it->second.host->data(), f->grid, cnt * sizeof(float)) != 0) {
+      bpm_ctx::FieldGrid fg;
+      auto host = std::make_shared<std::vector<float>>(f->grid, f->grid + cnt);
+      HIPCHK(c, hipSetDevice(c->device));
+      HIPCHK(c, hipMalloc(&fg.dev, sizeof(float) * cnt));
+      HIPCHK(c, hipMemcpy(fg.dev, host->data(), sizeof(float) * cnt, hipMemcpyHostToDevice));
+      fg.host = host;
+      fg.n[0] = f->nx; fg.n[1] = f->ny; fg.n[2] = f->nz;
+      while (c->grids.count(hsh)) ++hsh;   // a hash collision keeps both grids
+      it = c->grids.emplace(hsh, fg).first;
+    }
+    k.grid = it->second.dev;
+    I.grid_host = it->second.host;
+    for (int d = 0; d < 3; ++d) { k.gorig[d] = f->g_origin[d]; k.gn[d] = it->second.n[d]; }
+    k.gh = f->g_h;
+  }
   if (m0) I.m0.resize(3 * (size_t)g.n);   // no vector kept for the default state (+z everywhere)
   for (int i = 0; m0 && i < g.n; ++i) {
     double a = m0[i], b = m0[g.n + i], d = m0[2 * g.n + i];
@@ -890,7 +934,7 @@ static int run_heun_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream)
     h.rowptr = d.rowptr; h.col = d.col; h.colx = d.colx; h.K = d.K; h.D = d.D; h.DT = d.DT;
     h.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
     if (!h.S) return fail(c, BPM_EINVAL, "bpm_run: BPM_HEUN needs the row-major S in the run precision (BPM_KEEP_S64 / BPM_KEEP_S32)");
-    h.V = d.V; h.layer = d.layer; h.partner = d.partner; h.aif = d.aif; h.x = d.x; h.y = d.y;
+    h.V = d.V; h.layer = d.layer; h.partner = d.partner; h.aif = d.aif; h.x = d.x; h.y = d.y; h.z = d.z;
     h.Vsoft = g.vol_layer[0]; h.Vhard = g.vol_layer[1];
     const size_t cs = (size_t)g.n * R;
     HIPCHK(c, A.alloc(&h.m, 3 * cs));
@@ -1170,16 +1214,12 @@ int bpm_sync(bpm_ctx* c) {
   return BPM_OK;
 }
 
-static double applied_mag(const InstConst& k, const MeshGroup& g, double t) {
-  double amp = k.B_peak * (k.t_rise > 0.0 ? std::min(t / k.t_rise, 1.0) : 1.0);
-  if (k.fkind == BPM_FIELD_POLE) {
-    const double sx = g.centroid[0] + k.off[0] - k.x_off[0] - k.v[0] * t;
-    const double sy = g.centroid[1] + k.off[1] - k.x_off[1] - k.v[1] * t;
-    amp *= 0.5 * (1.0 - std::tanh(sx / k.L_grad)) * 0.5 *
-           (std::tanh((sy + 0.5 * k.W_pole) / k.L_grad) - std::tanh((sy - 0.5 * k.W_pole) / k.L_grad));
-  }
+// |B_applied| at the island centroid at time t (host evaluation; grids from the host copy)
+static double applied_mag(const Instance& I, const MeshGroup& g, double t) {
+  InstConst k = I.c;
+  if (I.grid_host) k.grid = I.grid_host->data();
   double b[3];
-  for (int d = 0; d < 3; ++d) b[d] = amp * k.dir[d] + k.B_ext[d];
+  applied_field_at(k, t, g.centroid[0] + k.off[0], g.centroid[1] + k.off[1], g.centroid[2] + k.off[2], b[0], b[1], b[2]);
   return std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
 }
 
@@ -1197,7 +1237,7 @@ int bpm_get_results(bpm_ctx* c, int32_t n, const int32_t* ids, bpm_result* out) 
     r.status = so.status;
     r.switched = io.switched;
     r.t_sw = io.crossed ? io.t_sw : NAN;
-    r.B_sw = io.crossed ? applied_mag(c->insts[id].c, *c->meshes[c->insts[id].mesh], io.t_sw) : NAN;
+    r.B_sw = io.crossed ? applied_mag(c->insts[id], *c->meshes[c->insts[id].mesh], io.t_sw) : NAN;
     r.mz_soft = io.mz_soft;
     r.mz_hard = io.mz_hard;
     r.t_reached = so.t_reached;

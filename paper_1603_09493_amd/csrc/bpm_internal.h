@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -93,6 +94,11 @@ struct InstConst {
   int32_t fkind, pad_;
   double B_peak, dir[3], t_rise, v[3], x_off[3], L_grad, W_pole, B_ext[3];
   double off[3];      // island position offset
+  // gridded field (BPM_FIELD_GRID): [3][nz][ny][nx] tesla, node (i, j, k) at gorig + gh (i, j, k)
+  const float* grid;  // device copy (a host copy for host-side evaluation)
+  double gorig[3], gh;
+  int32_t gn[3], gpad_;
+  double gpad2_;
   uint32_t key[2];    // Philox key (seed low, seed high)
   int32_t group, sys, local;   // mesh group, system, index within the group
   int32_t pad2_;
@@ -101,6 +107,7 @@ struct InstConst {
 struct Instance {
   int32_t mesh = 0;
   InstConst c{};
+  std::shared_ptr<const std::vector<float>> grid_host;   // host copy of a gridded field
   std::vector<double> m0;   // [3][n]; empty means every node starts along +z
   int32_t sys = -1;         // -1: own system
   bool coupled = false;

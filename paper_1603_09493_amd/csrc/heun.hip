@@ -18,6 +18,7 @@
 
 #include "bpm_internal.h"
 #include "heun_internal.h"
+#include "field_eval.h"
 
 namespace bpm {
 
@@ -59,20 +60,6 @@ __device__ __forceinline__ void gauss3(uint2 key, unsigned long long step, uint3
   g[0] = r0 * cs;
   g[1] = r0 * sn;
   g[2] = r1 * cosf(6.283185307179586f * u3);
-}
-
-__device__ __forceinline__ void applied_field(const InstConst& c, double t, double x, double y, double& bx,
-                                              double& by, double& bz) {
-  double amp = c.B_peak * ((c.t_rise > 0.0) ? fmin(t / c.t_rise, 1.0) : 1.0);
-  if (c.fkind == BPM_FIELD_POLE) {
-    const double sx = x - c.x_off[0] - c.v[0] * t;
-    const double sy = y - c.x_off[1] - c.v[1] * t;
-    amp *= 0.5 * (1.0 - tanh(sx / c.L_grad)) * 0.5 *
-           (tanh((sy + 0.5 * c.W_pole) / c.L_grad) - tanh((sy - 0.5 * c.W_pole) / c.L_grad));
-  }
-  bx = amp * c.dir[0] + c.B_ext[0];
-  by = amp * c.dir[1] + c.B_ext[1];
-  bz = amp * c.dir[2] + c.B_ext[2];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -417,7 +404,7 @@ __device__ __forceinline__ void heun_C_item(const HeunGroup<real>& g, const Inst
   const real cd = -(real)kMu0 / Vi;
   Bx += cd * dx; By += cd * dy; Bz += cd * dz;
   double zx, zy, zz;
-  applied_field(ic, t, g.x[i] + ic.off[0], g.y[i] + ic.off[1], zx, zy, zz);
+  applied_field_at(ic, t, g.x[i] + ic.off[0], g.y[i] + ic.off[1], g.z[i] + ic.off[2], zx, zy, zz);
   Bx += (real)zx; By += (real)zy; Bz += (real)zz;
   // thermal field (same draw in both stages of the step)
   if (P.temperature > 0.0) {

@@ -27,6 +27,7 @@ struct HeunGroup {
   const real* aif;
   const double* x;
   const double* y;
+  const double* z;
   double Vsoft, Vhard;
   real* m;       // [3][N][R] state at the start of the step
   real* yt;      // predictor

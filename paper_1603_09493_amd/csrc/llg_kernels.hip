@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "bpm_internal.h"
+#include "field_eval.h"
 
 namespace bpm {
 
@@ -165,33 +166,23 @@ __device__ __forceinline__ void group_sync(GroupSync& s) {
   __syncthreads();
 }
 
-__device__ __forceinline__ double rise_of(const InstConst& c, double t) {
-  if (!(c.t_rise > 0.0)) return 1.0;
-  const double r = t / c.t_rise;
-  return r < 1.0 ? r : 1.0;
-}
-
-// Applied field (tesla) at world position (x, y) and time t.
-__device__ __forceinline__ void applied_B(const InstConst& c, double t, double x, double y,
+// Applied field (tesla) at world position (x, y, z) and time t (field_eval.h).
+__device__ __forceinline__ void applied_B(const InstConst& c, double t, double x, double y, double z,
                                           double& bx, double& by, double& bz) {
-  double amp = c.B_peak * rise_of(c, t);
-  if (c.fkind == BPM_FIELD_POLE) {
-    const double sx = x - c.x_off[0] - c.v[0] * t;
-    const double sy = y - c.x_off[1] - c.v[1] * t;
-    const double fx = 0.5 * (1.0 - tanh(sx / c.L_grad));
-    const double fy = 0.5 * (tanh((sy + 0.5 * c.W_pole) / c.L_grad) - tanh((sy - 0.5 * c.W_pole) / c.L_grad));
-    amp *= fx * fy;
-  }
-  bx = amp * c.dir[0] + c.B_ext[0];
-  by = amp * c.dir[1] + c.B_ext[1];
-  bz = amp * c.dir[2] + c.B_ext[2];
+  applied_field_at(c, t, x, y, z, bx, by, bz);
 }
 
 // The same field with the profile evaluated in FP32 (positions and times stay FP64), for FP32
 // runs: its rounding (~1e-7) is far below their tolerance.
-__device__ __forceinline__ void applied_B_f32(const InstConst& c, double t, double x, double y,
+__device__ __forceinline__ void applied_B_f32(const InstConst& c, double t, double x, double y, double z,
                                               float& bx, float& by, float& bz) {
-  float amp = (float)(c.B_peak * rise_of(c, t));
+  if (c.fkind == BPM_FIELD_GRID) {
+    double gx, gy, gz;
+    applied_field_at(c, t, x, y, z, gx, gy, gz);
+    bx = (float)gx; by = (float)gy; bz = (float)gz;
+    return;
+  }
+  float amp = (float)(c.B_peak * field_rise(c, t));
   if (c.fkind == BPM_FIELD_POLE) {
     const float il = (float)(1.0 / c.L_grad);
     const float sx = (float)(x - c.x_off[0] - c.v[0] * t) * il;
@@ -709,12 +700,14 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
   // Zeeman (+ dipoles)
   if constexpr (sizeof(real) == 4) {
     float zx, zy, zz;
-    applied_B_f32(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
+    const double zi = ic.fkind == BPM_FIELD_GRID ? glb(g.z)[i] + ic.off[2] : 0.0;
+    applied_B_f32(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zi, zx, zy, zz);
     if (c.coupled[r]) { zx += (float)c.Bdip[r][0]; zy += (float)c.Bdip[r][1]; zz += (float)c.Bdip[r][2]; }
     Bx += zx; By += zy; Bz += zz;
   } else {
     double zx, zy, zz;
-    applied_B(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zx, zy, zz);
+    const double zi = ic.fkind == BPM_FIELD_GRID ? glb(g.z)[i] + ic.off[2] : 0.0;
+    applied_B(ic, ts, cs.x[k] + ic.off[0], cs.y[k] + ic.off[1], zi, zx, zy, zz);
     if (c.coupled[r]) { zx += c.Bdip[r][0]; zy += c.Bdip[r][1]; zz += c.Bdip[r][2]; }
     Bx += (real)zx; By += (real)zy; Bz += (real)zz;
   }
@@ -863,7 +856,7 @@ __device__ __forceinline__ void save_sample(const GroupView<real>& g, const RunP
   const int gi = g.inst0 + r;
   const InstConst& ic = icL[r];
   double bx, by, bz;
-  applied_B(ic, t, g.cen[0] + ic.off[0], g.cen[1] + ic.off[1], bx, by, bz);
+  applied_B(ic, t, g.cen[0] + ic.off[0], g.cen[1] + ic.off[1], g.cen[2] + ic.off[2], bx, by, bz);
   double* smp = P.traj + ((size_t)gi * P.traj_cap + c.ntraj[r]) * kTrajW;
   double wsum = ic.Ms[0] * g.Vsoft + ic.Ms[1] * g.Vhard;
   smp[0] = t;
@@ -1330,7 +1323,7 @@ __global__ __launch_bounds__(256) void energy_kernel(const GroupView<real>* __re
     if (p >= 0 && L == 0)
       e_loc += -ic.Jint * (double)g.aif[i] * (mi[0] * (double)m[p] + mi[1] * (double)m[n + p] + mi[2] * (double)m[2 * n + p]);
     double bx, by, bz;
-    applied_B(ic, t, g.x[i] + ic.off[0], g.y[i] + ic.off[1], bx, by, bz);
+    applied_B(ic, t, g.x[i] + ic.off[0], g.y[i] + ic.off[1], g.z[i] + ic.off[2], bx, by, bz);
     e_loc += -ic.Ms[L] * Vi * (mi[0] * bx + mi[1] * by + mi[2] * bz);
   }
   __syncthreads();

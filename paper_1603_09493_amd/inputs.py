@@ -31,6 +31,7 @@ NM = 1e-9
 # Field kinds understood by both solvers.
 FIELD_UNIFORM = 0
 FIELD_POLE = 1
+FIELD_GRID = 2
 
 LAYER_SOFT = 0
 LAYER_HARD = 1
@@ -72,6 +73,9 @@ class Field:
 
     kind = FIELD_UNIFORM:  B(t) = B_peak * r(t) * dir + B_ext
     kind = FIELD_POLE:     B(x, t) = B_peak * r(t) * fx(x - x_off - v t) * fy(y - y_off - v_y t) * dir + B_ext
+    kind = FIELD_GRID:     B(x, t) = B_peak * r(t) * G(x - x_off - v t) + B_ext, G the trilinear
+                           interpolation of `grid` ([3][nz][ny][nx] float32, node (i, j, k) at
+                           g_origin + g_h (i, j, k); zero outside)
     with r(t) = min(t / t_rise, 1).
     """
     kind: int = FIELD_UNIFORM
@@ -83,6 +87,28 @@ class Field:
     L_grad: float = 10e-9
     W_pole: float = 13e-9
     B_ext: tuple = (0.0, 0.0, 0.0)
+    grid: object = None                 # FIELD_GRID: float32 [3][nz][ny][nx]
+    g_origin: tuple = (0.0, 0.0, 0.0)
+    g_h: float = 2.5e-9
+
+
+def pole_field_grid(B_peak: float, dir, L_grad: float, W_pole: float, lo, hi, h: float = 2.5e-9):
+    """The synthetic pole head field sampled on a grid in its own frame: node values
+    B_peak * fx(s_x) * fy(s_y) * dir (tesla) with fx = (1 - tanh(s_x / L)) / 2 and
+    fy = (tanh((s_y + W/2) / L) - tanh((s_y - W/2) / L)) / 2 -- the form in which a precomputed
+    head field is handed to the recording simulation, here at the paper's 2.5 nm spacing.
+    Returns (grid float32 [3][nz][ny][nx], origin, h) covering the box [lo, hi]."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    n = np.maximum(2, np.ceil((hi - lo) / h).astype(int) + 1)
+    xs, ys = lo[0] + h * np.arange(n[0]), lo[1] + h * np.arange(n[1])
+    fx = 0.5 * (1.0 - np.tanh(xs / L_grad))
+    fy = 0.5 * (np.tanh((ys + 0.5 * W_pole) / L_grad) - np.tanh((ys - 0.5 * W_pole) / L_grad))
+    prof = B_peak * fy[:, None] * fx[None, :]                     # [ny][nx]
+    g = np.empty((3, n[2], n[1], n[0]), dtype=np.float32)
+    for d in range(3):
+        g[d] = (dir[d] * prof)[None, :, :]
+    return g, tuple(float(v) for v in lo), float(h)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -283,6 +309,94 @@ def patch_workload(seed: int = 1, n_target: int = 2000, sigma_rel: float = 0.05)
                           t_rise=0.1e-9, v=(20.0, 0.0, 0.0), x_off=(-10 * NM, 0.0, 0.0),
                           L_grad=10 * NM, W_pole=2 * py))
     return mesh, mats, flds, np.array(offs, dtype=np.float64)
+
+
+# Recording geometry of the 4 Tb/in^2 media (Sec. II.B, Fig. 3) and of the write simulations
+# (Sec. II.C): pseudo-hexagonal islands, 13.5 nm down-track and 11.7 nm cross-track pitch, 12 nm
+# dots of 12 nm height (soft + 1 nm interlayer + hard), J_S = 0.7 T in both phases,
+# K_1,soft = 0.2 K_1,hard; the head moves at 13.5 m/s, so one bit period is 1 ns.
+MEDIA_PITCH_DOWN = 13.5 * NM
+MEDIA_PITCH_CROSS = 11.7 * NM
+MEDIA_DOT = 12.0 * NM
+MEDIA_INTERLAYER = 1.0 * NM
+MEDIA_LAYER = 0.5 * (12.0 * NM - MEDIA_INTERLAYER)      # soft and hard thickness (equal split)
+MEDIA_JS = 0.7                                          # tesla
+HEAD_VELOCITY = 13.5                                    # m/s, down-track (+x)
+BIT_PERIOD = MEDIA_PITCH_DOWN / HEAD_VELOCITY           # 1 ns
+HEAD_RISE = 0.1e-9
+
+
+def recording_layout(p_down: float = MEDIA_PITCH_DOWN, p_cross: float = MEDIA_PITCH_CROSS) -> dict:
+    """Island centres (x down-track, y cross-track, metres) relative to the target bit.
+
+    The head travels in +x, so the previously written bit lies one down-track pitch behind the
+    target.  Neighbouring tracks of the pseudo-hexagonal pattern are shifted by half a
+    down-track pitch; `adjacent` is the nearest island of the next track."""
+    return {"target": (0.0, 0.0, 0.0), "previous": (-p_down, 0.0, 0.0),
+            "adjacent": (0.5 * p_down, p_cross, 0.0)}
+
+
+def media_mesh(n_target: int = 600, seed: int = 0, d: float = MEDIA_DOT, t_soft: float = MEDIA_LAYER,
+               t_hard: float = MEDIA_LAYER) -> Mesh:
+    """One cylindrical island of the media (hard layer z in [0, t_hard], soft on top)."""
+    return island_mesh_target(0.5 * d, 0.5 * d, t_soft, t_hard, n_target, seed=seed)
+
+
+def media_material(K_hard: float = 0.8e6, A_int: float = 2e-12, alpha: float = 0.1,
+                   A: float = 10e-12) -> Material:
+    """Material of the media islands: J_S = 0.7 T in both phases, K_1,soft = K_1,hard / 5, the
+    interlayer coupling A_int acting across a 1 nm interlayer (K_1,hard and A_int are design
+    parameters of the optimisation; the paper's initial values are the defaults)."""
+    Ms = MEDIA_JS / (4e-7 * math.pi)
+    return Material(Ms=(Ms, Ms), K=(0.2 * K_hard, K_hard), A=(A, A), A_int=A_int,
+                    delta_int=MEDIA_INTERLAYER, alpha=alpha)
+
+
+def write_head_grid(B_peak: float, dir, L_grad: float, W_pole: float, P_len: float, z_top: float,
+                    z_decay: float, lo, hi, h: float = 2.5e-9):
+    """A synthetic write-head field sampled on a grid in the head's own frame, standing in for the
+    precomputed head field of Sec. II.A (same 2.5 nm spacing).  Node values are
+    B_peak * fx(s_x) * fy(s_y) * fz(s_z) * dir with a pole of down-track length P_len whose
+    trailing edge sits at s_x = 0 (the head moves in +x):
+      fx = (tanh(s_x / L) - tanh((s_x - P_len) / L)) / 2,
+      fy = (tanh((s_y + W/2) / L) - tanh((s_y - W/2) / L)) / 2,
+      fz = exp((s_z - z_top) / z_decay)  (the field weakens away from the air-bearing surface).
+    Returns (grid float32 [3][nz][ny][nx], origin, h) covering the box [lo, hi]."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    n = np.maximum(2, np.ceil((hi - lo) / h).astype(int) + 1)
+    xs, ys, zs = (lo[d] + h * np.arange(n[d]) for d in range(3))
+    fx = 0.5 * (np.tanh(xs / L_grad) - np.tanh((xs - P_len) / L_grad))
+    fy = 0.5 * (np.tanh((ys + 0.5 * W_pole) / L_grad) - np.tanh((ys - 0.5 * W_pole) / L_grad))
+    fz = np.exp((zs - z_top) / z_decay)
+    prof = B_peak * fz[:, None, None] * fy[None, :, None] * fx[None, None, :]      # [nz][ny][nx]
+    g = np.empty((3, n[2], n[1], n[0]), dtype=np.float32)
+    for d in range(3):
+        g[d] = dir[d] * prof
+    return g, tuple(float(v) for v in lo), float(h)
+
+
+def default_head_grid(B_peak: float = 1.6, psi_deg: float = 25.0):
+    """The synthetic head used by the write-error driver: 1.6 T peak, tilted psi from -z toward
+    +x, 10 nm pole length and width, 4 nm edge length, 25 nm decay below the soft-layer top,
+    sampled over [-40, 50] x [-30, 30] x [-2.5, 15] nm."""
+    psi = math.radians(psi_deg)
+    d = (math.sin(psi), 0.0, -math.cos(psi))
+    return write_head_grid(B_peak, d, 4 * NM, 10 * NM, 10 * NM, 2 * MEDIA_LAYER, 25 * NM,
+                           lo=(-40 * NM, -30 * NM, -2.5 * NM), hi=(50 * NM, 30 * NM, 15 * NM))
+
+
+def recording_field(grid, g_origin, g_h, down_offset: float = 6.8 * NM, cross_offset: float = 0.0,
+                    p_down: float = MEDIA_PITCH_DOWN, v: float = HEAD_VELOCITY, t_rise: float = HEAD_RISE,
+                    B_ext=(0.0, 0.0, 0.0)) -> Field:
+    """The moving head field of one write period: the field switches on at t = 0 (rise t_rise)
+    and the trailing edge travels from down_offset - p_down to down_offset (relative to the target
+    centre) at speed v, so that it ends the period down_offset past the target, where it started
+    relative to the previous bit.  cross_offset shifts the head across the track (Table I's
+    down- and cross-track offsets)."""
+    return Field(kind=FIELD_GRID, B_peak=1.0, dir=(0.0, 0.0, -1.0), t_rise=t_rise, v=(v, 0.0, 0.0),
+                 x_off=(down_offset - p_down, cross_offset, 0.0), B_ext=tuple(B_ext), grid=grid,
+                 g_origin=tuple(g_origin), g_h=g_h)
 
 
 # Design-vector layout used by the batched designs and the surrogate:
