@@ -58,6 +58,7 @@ typedef struct {
   int32_t integrator, save_every;
   double t_end, dt0, dt_fixed, rtol, atol, dt_min, temperature;
   int64_t max_steps;
+  int32_t relax, pad_;         /* relax != 0: no precession term (energy descent) */
 } or_opts;
 
 typedef struct {
@@ -535,8 +536,10 @@ int or_fields(const or_mesh *M, const double *S, const or_material *mat, const o
 /* ------------------------------------------------------------------------------------------ */
 /* LLG right-hand side (Landau-Lifshitz form of the Gilbert equation, Sec. II.A):              */
 /*   dm/dt = -gamma/(1+alpha^2) [ m x B + alpha m x (m x B) ]                                 */
+/* prec = 0 drops the precession term m x B: the damping term alone moves m down the energy   */
+/* (the relaxation used by the string method for the energy barrier of Sec. II.C).            */
 /* ------------------------------------------------------------------------------------------ */
-static void llg_rhs(int n, double alpha, const double *m, const double *B, double *dm) {
+static void llg_rhs(int n, double alpha, double prec, const double *m, const double *B, double *dm) {
   double gp = OR_GAMMA / (1.0 + alpha * alpha);
   for (int i = 0; i < n; i++) {
     double mi[3] = {m[i], m[n + i], m[2 * n + i]};
@@ -544,12 +547,12 @@ static void llg_rhs(int n, double alpha, const double *m, const double *B, doubl
     double mxb[3], mxmxb[3];
     cross3(mi, b, mxb);
     cross3(mi, mxb, mxmxb);
-    for (int c = 0; c < 3; c++) dm[c * n + i] = -gp * (mxb[c] + alpha * mxmxb[c]);
+    for (int c = 0; c < 3; c++) dm[c * n + i] = -gp * (prec * mxb[c] + alpha * mxmxb[c]);
   }
 }
 
 int or_llg_rhs(int n, double alpha, const double *m, const double *B, double *dm) {
-  llg_rhs(n, alpha, m, B, dm);
+  llg_rhs(n, alpha, 1.0, m, B, dm);
   return OR_OK;
 }
 
@@ -604,6 +607,7 @@ typedef struct {
   double *Bbuf;                /* [3n] */
   double *Bdip;                /* [R][3] */
   double *mom;                 /* [R][3] */
+  int relax;                   /* drop the precession term */
 } or_system;
 
 static void sys_init(or_system *Y) {
@@ -647,7 +651,7 @@ static void sys_rhs(or_system *Y, double t, const double *y, const double *Bth, 
     field_terms(Y->M, Y->S, &Y->mat[r], &Y->fld[r], Y->off + 3 * r, t, m, Y->Bdip + 3 * r,
                 Y->Bbuf, NULL, NULL, &Y->W);
     if (Bth) for (int i = 0; i < 3 * n; i++) Y->Bbuf[i] += Bth[(size_t)r * 3 * n + i];
-    llg_rhs(n, Y->mat[r].alpha, m, Y->Bbuf, dy + (size_t)r * 3 * n);
+    llg_rhs(n, Y->mat[r].alpha, Y->relax ? 0.0 : 1.0, m, Y->Bbuf, dy + (size_t)r * 3 * n);
   }
 }
 
@@ -945,6 +949,7 @@ int or_run(const or_mesh *M, const double *S, int R, const or_material *mats,
   for (int r = 0; r < R; r++) if (ntraj) ntraj[r] = 0;
   if (coupled && R > 1) {
     or_system Y = {M, S, R, mats, flds, offsets, 1};
+    Y.relax = o->relax;
     sys_init(&Y);
     if (o->integrator == OR_HEUN) run_heun(&Y, o, seeds, m, res, traj, cap, ntraj);
     else run_dp5(&Y, o, m, res, traj, cap, ntraj);
@@ -953,6 +958,7 @@ int or_run(const or_mesh *M, const double *S, int R, const or_material *mats,
 #pragma omp parallel for schedule(dynamic, 1)
     for (int r = 0; r < R; r++) {
       or_system Y = {M, S, 1, mats + r, flds + r, offsets ? offsets + 3 * r : zero3, 0};
+      Y.relax = o->relax;
       sys_init(&Y);
       double *trr = traj ? traj + (size_t)r * cap * 9 : NULL;
       int64_t *ntr = ntraj ? ntraj + r : NULL;

@@ -44,7 +44,7 @@ class Opts(C.Structure):
     _fields_ = [("integrator", C.c_int32), ("save_every", C.c_int32), ("t_end", C.c_double),
                 ("dt0", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double),
                 ("atol", C.c_double), ("dt_min", C.c_double), ("temperature", C.c_double),
-                ("max_steps", C.c_int64)]
+                ("max_steps", C.c_int64), ("relax", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -226,6 +226,7 @@ class OracleMesh:
         o.dt_min = opts.get("dt_min", 1e-19)
         o.temperature = opts.get("temperature", 0.0)
         o.max_steps = opts.get("max_steps", 0)
+        o.relax = 1 if opts.get("relax", False) else 0
         res = (Result * R)()
         cap = int(traj_cap)
         traj = np.zeros((R, max(cap, 1), 9))
