@@ -187,7 +187,10 @@ enum { BPM_FLAG_SYMMETRIC_DEMAG = 1,
                                  runs of several mesh groups, else 256 unless tuned) */
        BPM_FLAG_STREAM_S = 4, /* stream S from global memory even where its rows fit in LDS */
        BPM_FLAG_WG256 = 8,    /* 256-thread workgroups whatever the default */
-       BPM_FLAG_CONTINUE = 16 /* continue the previous DP5 run (see below) */ };
+       BPM_FLAG_CONTINUE = 16, /* continue the previous DP5 run (see below) */
+       BPM_FLAG_RELAX = 32     /* DP5 runs without the precession term: dm/dt = -gamma alpha /
+                                  (1 + alpha^2) m x (m x B), a descent of the total energy (the
+                                  relaxation step of the string method, bpm_string_reparam) */ };
 
 /* BPM_FLAG_CONTINUE: instead of starting from m0 at t = 0, the run continues the last
  * BPM_DP45 / BPM_DP5_FIXED run of this context up to the new t_end (>= the previous end): the
@@ -247,6 +250,26 @@ int bpm_last_run_info(bpm_ctx* ctx, double* kernel_ms, int32_t* grid, int32_t* w
 int bpm_last_run_layout(bpm_ctx* ctx, int32_t* threads_per_wg, int32_t* s_rows_lds, int32_t* csr_cap_lds,
                         int32_t* rhs_block, int64_t* lds_bytes);
 
+
+/* ------------------------------------------------------------------------------------------ */
+/* Energy barrier: string method                                                              */
+/* ------------------------------------------------------------------------------------------ */
+/* The paper computes the energy barrier of the adjacent bit in the head's fringing field with a
+ * minimum-energy-path method (nudged elastic band, Sec. II.C); here the simplified string
+ * method runs on the same field and energy kernels.  A string is a chain of P images
+ * m^0..m^{P-1} of one island (P instances on one mesh group, in chain order).  One iteration
+ * relaxes every image by a BPM_FLAG_RELAX run and then calls bpm_string_reparam, which moves the
+ * images back to equal spacing along the chain:
+ *   d_k = || m^{k+1} - m^k ||_2 over all 3n node components, s_k = d_0 + ... + d_{k-1},
+ *   image j goes to arc length j s_{P-1} / (P - 1), by linear interpolation between the two
+ *   images whose arc lengths bracket it, and every node vector is normalised
+ * (the end images stay where they are).  It reads the final magnetisation of the last
+ * synchronised DP5 run, which must have run the current instance set (BPM_ESTATE otherwise),
+ * computes on the GPU in FP64, and stores the new images as the instances' m0, so that the next
+ * fresh run starts from them.  arclen (host, P values, may be NULL) receives s_0..s_{P-1} of the
+ * images before the redistribution; the energies of those images are the bpm_result energies
+ * of that run.  3 <= P <= 64.  Synchronous. */
+int bpm_string_reparam(bpm_ctx* ctx, int32_t n_images, const int32_t* ids, double* arclen);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Learned screen                                                                             */

@@ -24,6 +24,7 @@ FLAG_WG512 = 2
 FLAG_STREAM_S = 4
 FLAG_WG256 = 8
 FLAG_CONTINUE = 16
+FLAG_RELAX = 32
 KEEP_S64, KEEP_S32, KEEP_S32_TILES = 1, 2, 4
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
@@ -76,7 +77,7 @@ SYMBOLS = [
     "bpm_create", "bpm_destroy", "bpm_last_error", "bpm_mesh_add", "bpm_mesh_add_ex", "bpm_mesh_get_S",
     "bpm_mesh_get_assembly", "bpm_instance_add", "bpm_couple_dipoles", "bpm_clear_instances",
     "bpm_run", "bpm_sync", "bpm_autotune", "bpm_get_results", "bpm_get_trajectory", "bpm_get_m", "bpm_last_run_info",
-    "bpm_last_run_layout",
+    "bpm_last_run_layout", "bpm_string_reparam",
 ]
 
 EXTRA_SYMBOLS = [
@@ -123,6 +124,7 @@ def lib():
     L.bpm_get_results.argtypes = [P, I32, P, P]
     L.bpm_get_trajectory.argtypes = [P, I32, P, I64, C.POINTER(I64)]
     L.bpm_get_m.argtypes = [P, I32, P, I32]
+    L.bpm_string_reparam.argtypes = [P, I32, P, P]
     L.bpm_last_run_info.argtypes = [P, C.POINTER(D), C.POINTER(I32), C.POINTER(I32)]
     L.bpm_last_run_layout.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]
     L.bpm_mlp_num_params.argtypes = []
@@ -308,6 +310,15 @@ class Context:
         host = np.empty((3, n))
         self._check(self.L.bpm_get_m(self.h, iid, _p(host), 0))
         return host
+
+    def string_reparam(self, ids):
+        """Moves the images `ids` (chain order, final states of the last run) back to equal spacing
+        along the chain and stores them as the instances' m0; returns the arc lengths of the
+        images before the move."""
+        a = np.ascontiguousarray(ids, dtype=np.int32)
+        s = np.empty(len(a))
+        self._check(self.L.bpm_string_reparam(self.h, len(a), _p(a), _p(s)))
+        return s
 
     def last_run_info(self):
         ms = C.c_double(); grid = C.c_int32(); G = C.c_int32()

@@ -28,6 +28,8 @@ void pack_tiles_device(int n, int ldS, const double* S, float* T, hipStream_t st
 hipError_t extract_m_device(int precision, long n, long rstride, long offset, const void* src, double* dst,
                             hipStream_t stream);
 void symmetrize_device(int n, int ldS, double* S, hipStream_t stream);
+hipError_t string_reparam_device(int precision, long n, int P, const StringImages& im, double* d_dist,
+                                 double* d_out, hipStream_t stream);
 
 template <typename real>
 size_t dp5_lds_bytes(const LdsPlan&);
@@ -1299,6 +1301,56 @@ int bpm_get_m(bpm_ctx* c, int32_t id, void* dst, int32_t dst_is_device) {
   for (long comp = 0; comp < 3; ++comp)
     for (long i = 0; i < n; ++i)
       m_out[comp * n + i] = c->run_rfast ? all[(size_t)(comp * n + i) * rstride + offset] : all[(size_t)(comp * n + i)];
+  return BPM_OK;
+}
+
+int bpm_string_reparam(bpm_ctx* c, int32_t P, const int32_t* ids, double* arclen) {
+  if (!c) return BPM_EINVAL;
+  if (!ids || P < 3 || P > kStringMaxImages)
+    return fail(c, BPM_EINVAL, "bpm_string_reparam: need 3..64 image ids");
+  if (!c->have_results || c->run_rfast || c->run_version != c->inst_version)
+    return fail(c, BPM_ESTATE, "bpm_string_reparam: the last synchronised run must be a DP5 run of the current instances");
+  int mi = -1;
+  StringImages im{};
+  for (int k = 0; k < P; ++k) {
+    const int id = ids[k];
+    if (id < 0 || id >= (int)c->slot_of.size() || c->slot_of[id] < 0)
+      return fail(c, BPM_EINVAL, "bpm_string_reparam: bad instance id");
+    for (int l = 0; l < k; ++l)
+      if (ids[l] == id) return fail(c, BPM_EINVAL, "bpm_string_reparam: an image appears twice");
+    const int s = c->slot_of[id];
+    if (mi >= 0 && c->slot_group[s] != mi)
+      return fail(c, BPM_EINVAL, "bpm_string_reparam: the images must share one mesh group");
+    mi = c->slot_group[s];
+    const size_t off = (size_t)c->slot_local[s] * 3 * c->meshes[mi]->n;
+    im.p[k] = c->run_precision == 64 ? (const void*)(reinterpret_cast<const double*>(c->group_m[mi]) + off)
+                                     : (const void*)(reinterpret_cast<const float*>(c->group_m[mi]) + off);
+  }
+  const long n = c->meshes[mi]->n;
+  HIPCHK(c, hipSetDevice(c->device));
+  double *d_dist = nullptr, *d_out = nullptr;
+  HIPCHK(c, hipMalloc(&d_dist, sizeof(double) * P));
+  hipError_t e = hipMalloc(&d_out, sizeof(double) * 3 * n * P);
+  if (e == hipSuccess) e = string_reparam_device(c->run_precision, n, P, im, d_dist, d_out, c->own_stream);
+  std::vector<double> h_out, h_d(P - 1);
+  if (e == hipSuccess) {
+    h_out.resize((size_t)3 * n * P);
+    e = hipMemcpyAsync(h_out.data(), d_out, sizeof(double) * h_out.size(), hipMemcpyDeviceToHost, c->own_stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h_d.data(), d_dist, sizeof(double) * (P - 1), hipMemcpyDeviceToHost, c->own_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->own_stream);
+  hipFree(d_dist);
+  if (d_out) hipFree(d_out);
+  HIPCHK(c, e);
+  for (int k = 0; k < P; ++k) {
+    Instance& I = c->insts[ids[k]];
+    I.m0.assign(h_out.begin() + (size_t)k * 3 * n, h_out.begin() + (size_t)(k + 1) * 3 * n);
+  }
+  if (arclen) {
+    arclen[0] = 0.0;
+    for (int k = 1; k < P; ++k) arclen[k] = arclen[k - 1] + h_d[k - 1];
+  }
   return BPM_OK;
 }
 

@@ -58,6 +58,12 @@ constexpr double kBoltzmann = 1.380649e-23;    // J / K
 
 constexpr int kMaxSysPerGroup = 64;   // adaptive-control state is replicated in LDS per group
 constexpr int kMaxInstPerGroup = 64;
+constexpr int kStringMaxImages = 64;   // images of one string (bpm_string_reparam)
+
+// Device pointers of the images of one string, in chain order (a kernel argument).
+struct StringImages {
+  const void* p[kStringMaxImages];
+};
 constexpr int kBlock = 256;           // threads per workgroup of the stepping kernels
 constexpr int kTrajW = 9;             // trajectory sample width
 

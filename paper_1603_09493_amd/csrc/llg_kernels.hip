@@ -711,10 +711,12 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
     if (c.coupled[r]) { zx += c.Bdip[r][0]; zy += c.Bdip[r][1]; zz += c.Bdip[r][2]; }
     Bx += (real)zx; By += (real)zy; Bz += (real)zz;
   }
-  // LLG: dm/dt = -gp [ m x B + alpha m x (m x B) ]
+  // LLG: dm/dt = -gp [ m x B + alpha m x (m x B) ]; relaxation runs drop the precession term and
+  // so descend the energy along -m x (m x B)
   const real cx = my * Bz - mz * By, cy = mz * Bx - mx * Bz, cz = mx * By - my * Bx;
   const real dx2 = my * cz - mz * cy, dy2 = mz * cx - mx * cz, dz2 = mx * cy - my * cx;
-  const real kx = -gp * (cx + al * dx2), ky = -gp * (cy + al * dy2), kz = -gp * (cz + al * dz2);
+  const real pr = (P.flags & BPM_FLAG_RELAX) ? (real)0 : (real)1;
+  const real kx = -gp * (pr * cx + al * dx2), ky = -gp * (pr * cy + al * dy2), kz = -gp * (pr * cz + al * dz2);
   GLB real* ks = kr + (size_t)s * st3;
   ks[i] = kx; ks[n + i] = ky; ks[2 * n + i] = kz;
   if (s < 6) {

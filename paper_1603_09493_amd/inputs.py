@@ -399,6 +399,27 @@ def recording_field(grid, g_origin, g_h, down_offset: float = 6.8 * NM, cross_of
                  g_origin=tuple(g_origin), g_h=g_h)
 
 
+def adjacent_field(grid, g_origin, g_h, layout=None, cross_offset: float = 0.0,
+                   te_distance: float = 2.0 * NM) -> Field:
+    """The static head field seen by the adjacent island (Sec. II.C): the head stands with its
+    trailing edge te_distance behind the island's centre in the flight direction (so the island
+    sits 2 nm inside the pole's down-track extent by default), shifted across the track by
+    cross_offset; the island itself is placed at layout["adjacent"]."""
+    layout = recording_layout() if layout is None else layout
+    xa = layout["adjacent"][0]
+    return Field(kind=FIELD_GRID, B_peak=1.0, dir=(0.0, 0.0, -1.0), t_rise=0.0, v=(0.0, 0.0, 0.0),
+                 x_off=(xa - te_distance, cross_offset, 0.0), grid=grid, g_origin=tuple(g_origin), g_h=g_h)
+
+
+def rotation_chain(n: int, P: int, via=(1.0, 0.0, 0.0)) -> np.ndarray:
+    """Initial string of P uniform states turning from +z to -z through the unit direction `via`
+    (perpendicular to z): image k at polar angle pi k / (P - 1).  Returns [P][3][n]."""
+    v = np.asarray(via, dtype=np.float64)
+    th = math.pi * np.arange(P) / (P - 1)
+    d = np.cos(th)[:, None] * np.array([0.0, 0.0, 1.0]) + np.sin(th)[:, None] * v      # [P][3]
+    return np.ascontiguousarray(np.repeat(d[:, :, None], n, axis=2))
+
+
 # Design-vector layout used by the batched designs and the surrogate:
 DESIGN_NAMES = ("d", "t_soft", "t_hard", "Ms_soft", "Ms_hard", "K_soft", "K_hard", "A_int",
                 "psi", "B_peak", "alpha", "t_rise")
