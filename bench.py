@@ -68,14 +68,15 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_ratio():
+def traffic_ratio(storage="fp32"):
     """(FETCH_SIZE + WRITE_SIZE) of the profiled stepping launch, scaled by the counters' reading
     for a device copy of known size, per algorithmic byte of that launch -- or None when the
-    summary is missing or was taken on another kernel source."""
-    if not os.path.exists(COUNTERS):
+    summary is missing or was taken on another kernel source or storage of S."""
+    path = COUNTERS if storage == "fp32" else COUNTERS.replace("_batch_", "_batch_%s_" % storage)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(COUNTERS) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -253,6 +254,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--full-demag", action="store_true", help="read all of S (default: its upper triangle)")
+    ap.add_argument("--demag-storage", choices=["fp32", "fp16"], default="fp32",
+                    help="storage of the packed upper-triangle tiles of S (arithmetic stays FP32)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run three device copies of this many MiB (scales the profiler's byte counters)")
     ap.add_argument("--cpu-slice-ps", type=float, default=16.0, help="simulated time per oracle island (ps)")
@@ -280,7 +283,11 @@ def main():
     ids, sizes, nnzs = [], [], []
     # the batch keeps its operators as FP32 packed upper-triangle tiles only (about half the bytes
     # of row-major S); --full-demag keeps the row-major FP32 copy for the full product
-    keep = bpm.KEEP_S32 if args.full_demag else bpm.KEEP_S32_TILES
+    # (--demag-storage fp16: the tiles in FP16, widened to FP32 in the product)
+    if args.full_demag and args.demag_storage != "fp32":
+        ap.error("--full-demag reads the row-major FP32 copy")
+    keep = bpm.KEEP_S32 if args.full_demag else (bpm.KEEP_S16_TILES if args.demag_storage == "fp16" else bpm.KEEP_S32_TILES)
+    s_entry = 2 if args.demag_storage == "fp16" else 4
     for q, (mesh, mat, fld) in enumerate(ins):
         mid = ctx.mesh_add(mesh, keep=keep)
         ids.append(ctx.instance_add(mid, mat, fld))
@@ -317,12 +324,12 @@ def main():
         att = np.array([r["n_accept"] + r["n_reject"] for r in res]) if res else np.zeros(1)
         sim_ns = done * args.slice_ps * 1e-3
         wall = state["wall"]
-        by = sum(roofline.eval_bytes(n, z, 1, 4, symmetric=not args.full_demag) * (6 * a + 1)
+        by = sum(roofline.eval_bytes(n, z, 1, 4, symmetric=not args.full_demag, ps=s_entry) * (6 * a + 1)
                  for n, z, a in zip(sizes, nnzs, att)) if res else 0.0
         fl = sum(roofline.eval_flops(n, z, 1) * (6 * a + 1) for n, z, a in zip(sizes, nnzs, att)) if res else 0.0
         k_s = state["kernel_ms"] * 1e-3
         achieved = by / k_s / 1e9 if k_s > 0 else 0.0
-        tr = traffic_ratio()
+        tr = traffic_ratio(args.demag_storage)
         out.update({
             "metric": METRIC,
             "value": args.islands * sim_ns / wall if wall > 0 else 0.0,
@@ -348,6 +355,7 @@ def main():
                 "slice_ps": args.slice_ps,
                 "steps_requested": args.steps,
                 "demag_product": "full S" if args.full_demag else "upper triangle of S, packed 64x64 tiles",
+                "demag_storage": args.demag_storage,
                 "switched_fraction": float(np.mean([r["switched"] for r in res])) if res else None,
                 "attempts_mean": float(att.mean()), "attempts_max": int(att.max()),
                 "status_ok": int(sum(r["status"] == 0 for r in res)) if res else 0,
@@ -358,7 +366,7 @@ def main():
             },
             "roofline": {
                 "bound": "hbm",
-                "kernel": "dp5_kernel (FP32, one 512-thread workgroup per island)",
+                "kernel": "dp5_kernel (FP32, one %d-thread workgroup per island)" % ctx.last_run_layout()["threads"],
                 "achieved": achieved,
                 "peak": roofline.MI355X_HBM_GBS,
                 "unit": "GB/s",

@@ -90,15 +90,21 @@ int bpm_mesh_add(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, doubl
  *                       of the row-major copy; read by the upper-triangle product of FP32 runs
  *                       with BPM_FLAG_SYMMETRIC_DEMAG and one workgroup per group (it is used for
  *                       them whenever kept).
- * A run needs a copy it can use (BPM_EINVAL otherwise): a group keeping only the packed tiles
- * runs only in such launches (not in BPM_HEUN runs or cooperative launches); large batches of
- * FP32 runs keep only the packed tiles. */
-enum { BPM_KEEP_S64 = 1, BPM_KEEP_S32 = 2, BPM_KEEP_S32_TILES = 4 };
+ *   BPM_KEEP_S16_TILES  the same tiles stored in FP16: S times a power-of-two scale (which puts
+ *                       the largest |S_kl| between 2^13 and 2^14) rounded to nearest, a quarter of
+ *                       the row-major FP32 bytes; the product widens every entry to FP32 and
+ *                       accumulates in FP32 (relative rounding of each entry <= 2^-11).  Used by
+ *                       the same launches when the FP32 tiles are not kept.
+ * A run needs a copy it can use (BPM_EINVAL otherwise): a group keeping only packed tiles runs
+ * only in such launches (not in BPM_HEUN runs or cooperative launches); large batches of FP32
+ * runs keep only the packed tiles. */
+enum { BPM_KEEP_S64 = 1, BPM_KEEP_S32 = 2, BPM_KEEP_S32_TILES = 4, BPM_KEEP_S16_TILES = 8 };
 int bpm_mesh_add_ex(bpm_ctx* ctx, const bpm_mesh* mesh, const double* S_host, double demag_beta,
                     int32_t flags, int32_t* mesh_id);
 
 /* Copies the group's demag operator to host memory S_out [n][n] (FP64, or the widened FP32 copy
- * if only that is kept, or both triangles unpacked from the packed tiles). */
+ * if only that is kept, or both triangles unpacked from the packed FP32 tiles, else from the
+ * FP16 tiles divided by their scale). */
 int bpm_mesh_get_S(bpm_ctx* ctx, int32_t mesh_id, double* S_out);
 
 /* Copies the host-assembled quantities of a group: V [n], rowptr [n+1], col [nnz], K [nnz],

@@ -25,7 +25,7 @@ FLAG_STREAM_S = 4
 FLAG_WG256 = 8
 FLAG_CONTINUE = 16
 FLAG_RELAX = 32
-KEEP_S64, KEEP_S32, KEEP_S32_TILES = 1, 2, 4
+KEEP_S64, KEEP_S32, KEEP_S32_TILES, KEEP_S16_TILES = 1, 2, 4, 8
 DP45, DP5_FIXED, HEUN = 0, 1, 2
 
 
@@ -212,7 +212,8 @@ class Context:
     # meshes -------------------------------------------------------------------------------------
     def mesh_add(self, mesh, S=None, beta=0.0, keep=3) -> int:
         """keep (bits): 1 = row-major FP64 demag operator, 2 = row-major FP32, 4 = FP32 upper-triangle
-        packed tiles (for the upper-triangle product of FP32 batches)."""
+        packed tiles (for the upper-triangle product of FP32 batches), 8 = the same tiles in FP16
+        (scaled by a power of two; used when the FP32 tiles are not kept)."""
         xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
         tet = np.ascontiguousarray(mesh.tet, dtype=np.int32)
         layer = np.ascontiguousarray(mesh.layer, dtype=np.int32)

@@ -25,6 +25,8 @@ std::string hip_err_string(hipError_t e) { return hipGetErrorString(e); }
 
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream);
 void pack_tiles_device(int n, int ldS, const double* S, float* T, hipStream_t stream);
+hipError_t absmax_device(size_t cnt, const double* a, float* out, hipStream_t stream);
+void pack_tiles16_device(int n, int ldS, const double* S, double scale, uint16_t* T, hipStream_t stream);
 hipError_t extract_m_device(int precision, long n, long rstride, long offset, const void* src, double* dst,
                             hipStream_t stream);
 void symmetrize_device(int n, int ldS, double* S, hipStream_t stream);
@@ -198,6 +200,7 @@ void bpm_destroy(bpm_ctx* c) {
     if (m->dS64) hipFree(m->dS64);
     if (m->dS32) hipFree(m->dS32);
     if (m->dS32t) hipFree(m->dS32t);
+    if (m->dS16t) hipFree(m->dS16t);
   }
   c->mesh_arena.clear();
   for (auto& kv : c->grids) hipFree(kv.second.dev);
@@ -265,7 +268,7 @@ int bpm_mesh_add(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double 
 
 int bpm_mesh_add_ex(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, double demag_beta, int32_t flags,
                     int32_t* mesh_id) {
-  if (c && !(flags & (BPM_KEEP_S64 | BPM_KEEP_S32 | BPM_KEEP_S32_TILES)))
+  if (c && !(flags & (BPM_KEEP_S64 | BPM_KEEP_S32 | BPM_KEEP_S32_TILES | BPM_KEEP_S16_TILES)))
     return fail(c, BPM_EINVAL, "bpm_mesh_add_ex: keep at least one copy of S");
   if (!c) return BPM_EINVAL;
   if (!mesh || !mesh_id || !mesh->xyz || !mesh->tet || !mesh->node_layer)
@@ -317,6 +320,21 @@ int bpm_mesh_add_ex(bpm_ctx* c, const bpm_mesh* mesh, const double* S_host, doub
     HIPCHK(c, hipMalloc(&g->dS32t, sizeof(float) * (size_t)tile_count(n) * kTile * kTile));
     pack_tiles_device(n, ldS, g->dS64, g->dS32t, c->own_stream);
   }
+  if (flags & BPM_KEEP_S16_TILES) {
+    // a power-of-two scale keeps the products exact and puts max |S| in [2^13, 2^14)
+    float* d_max = nullptr;
+    HIPCHK(c, hipMalloc(&d_max, sizeof(float)));
+    hipError_t e = absmax_device((size_t)n * ldS, g->dS64, d_max, c->own_stream);
+    float mx = 0.f;
+    if (e == hipSuccess) e = hipMemcpyAsync(&mx, d_max, sizeof(float), hipMemcpyDeviceToHost, c->own_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->own_stream);
+    hipFree(d_max);
+    HIPCHK(c, e);
+    if (!std::isfinite(mx)) return fail(c, BPM_EINVAL, "bpm_mesh_add: demag operator is not finite");
+    g->s16_scale = mx > 0.f ? std::ldexp(1.0, 13 - std::ilogb((double)mx)) : 1.0;
+    HIPCHK(c, hipMalloc(&g->dS16t, sizeof(uint16_t) * (size_t)tile_count(n) * kTile * kTile));
+    pack_tiles16_device(n, ldS, g->dS64, g->s16_scale, g->dS16t, c->own_stream);
+  }
   HIPCHK(c, hipStreamSynchronize(c->own_stream));
   if (!(flags & BPM_KEEP_S64)) {
     HIPCHK(c, hipFree(g->dS64));
@@ -338,6 +356,17 @@ int bpm_mesh_get_S(bpm_ctx* c, int32_t id, double* S_out) {
   if (g.dS64) {
     HIPCHK(c, hipMemcpy2D(S_out, sizeof(double) * g.n, g.dS64, sizeof(double) * ldS, sizeof(double) * g.n, g.n,
                           hipMemcpyDeviceToHost));
+  } else if (!g.dS32 && !g.dS32t) {
+    // only the packed FP16 tiles: unpack both triangles and undo the scale
+    const int nb = (g.n + kTile - 1) / kTile;
+    std::vector<_Float16> tmp((size_t)tile_count(g.n) * kTile * kTile);
+    HIPCHK(c, hipMemcpy(tmp.data(), g.dS16t, sizeof(uint16_t) * tmp.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < g.n; ++k)
+      for (int l = 0; l < g.n; ++l) {
+        const int a = std::min(k, l), b = std::max(k, l);
+        const size_t f = (size_t)tile_index(nb, a / kTile, b / kTile);
+        S_out[(size_t)k * g.n + l] = (double)tmp[f * kTile * kTile + tile16_offset(a % kTile, b % kTile)] / g.s16_scale;
+      }
   } else if (!g.dS32) {
     // only the packed FP32 tiles: unpack both triangles
     const int nb = (g.n + kTile - 1) / kTile;
@@ -716,9 +745,11 @@ static int run_typed(bpm_ctx* c, const bpm_run_opts* o, hipStream_t stream) {
     v.rowptr = d.rowptr; v.col = d.col; v.colx = d.colx; v.K = d.K; v.D = d.D; v.DT = d.DT;
     v.S = std::is_same<real, double>::value ? reinterpret_cast<const real*>(g.dS64) : reinterpret_cast<const real*>(g.dS32);
     v.St = std::is_same<real, float>::value ? g.dS32t : nullptr;
+    v.St16 = std::is_same<real, float>::value && !g.dS32t ? g.dS16t : nullptr;
+    v.s16_inv = (float)(1.0 / g.s16_scale);
     // the packed tiles serve only the upper-triangle product of single-workgroup groups
-    if (!v.S && !(v.St && sym && G[gi] == 1 && !coop))
-      return fail(c, BPM_EINVAL, v.St ? "bpm_run: a group keeping only the packed tiles of S needs "
+    if (!v.S && !((v.St || v.St16) && sym && G[gi] == 1 && !coop))
+      return fail(c, BPM_EINVAL, (v.St || v.St16) ? "bpm_run: a group keeping only the packed tiles of S needs "
                                         "BPM_FLAG_SYMMETRIC_DEMAG and one workgroup per group"
                                       : "bpm_run: a mesh group does not keep S in the run precision");
     v.V = d.V; v.layer = d.layer; v.partner = d.partner; v.aif = d.aif;

@@ -50,6 +50,14 @@ __host__ __device__ inline long tile_index(int nb, int I, int J) {   // I <= J
 __host__ __device__ inline int tile_offset(int r, int c) {
   return (((r & 15) * 4 + (r >> 4)) * 16 + (c >> 2)) * 4 + (c & 3);
 }
+// FP16 tiles (same tile order, 4096 halves each): element (r, c) with r = 16 rg + 2 u + v
+// (u < 8, v < 2) and c = 4 cq + q sits at (((4 u + rg) * 16 + cq) * 8 + 4 v + q: each 16-byte word
+// holds two rows of a lane's four columns, and the eight words of lane (rg, cq) are one word of
+// each of eight contiguous 1 KB blocks.
+__host__ __device__ inline int tile16_offset(int r, int c) {
+  const int t = r & 15;
+  return ((((t >> 1) * 4 + (r >> 4)) * 16 + (c >> 2)) * 8) + (t & 1) * 4 + (c & 3);
+}
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kMu0 = 4.0e-7 * kPi;          // T m / A
@@ -84,6 +92,8 @@ struct MeshGroup {
   double* dS64 = nullptr;                 // [n][n]
   float* dS32 = nullptr;
   float* dS32t = nullptr;                 // FP32 upper-triangle 64x64 tiles, packed (see kTile)
+  uint16_t* dS16t = nullptr;              // FP16 tiles of S * s16_scale (see tile16_offset)
+  double s16_scale = 1.0;
   bool S_ready = false;
 };
 
@@ -153,6 +163,8 @@ struct GroupView {
   const real* DT;             // [nnz][3]
   const real* S;              // [n][ldS] row-major (may be null when St is given)
   const float* St;            // FP32 packed upper-triangle tiles (null if not kept)
+  const uint16_t* St16;       // FP16 packed tiles of S * scale (used when St is null)
+  float s16_inv;              // 1 / scale of St16
   const real* V;
   const int32_t* layer;
   const int32_t* partner;

@@ -119,6 +119,47 @@ void pack_tiles_device(int n, int ldS, const double* S, float* T, hipStream_t st
   hipLaunchKernelGGL(pack_tiles_kernel, dim3((unsigned)tile_count(n)), dim3(256), 0, stream, n, ldS, nb, S, T);
 }
 
+// max |a| over cnt entries into *out (bit patterns of non-negative floats order like the values)
+__global__ void absmax_kernel(size_t cnt, const double* __restrict__ a, unsigned* __restrict__ out) {
+  float m = 0.f;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += (size_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, (float)fabs(a[q]));
+  for (int w = 32; w >= 1; w >>= 1) m = fmaxf(m, __shfl_xor(m, w, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+hipError_t absmax_device(size_t cnt, const double* a, float* out, hipStream_t stream) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(float), stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(absmax_kernel, dim3(512), dim3(256), 0, stream, cnt, a, reinterpret_cast<unsigned*>(out));
+  return hipGetLastError();
+}
+
+// FP16 packed tiles of S * scale (layout: tile16_offset); one workgroup per tile
+__global__ void pack_tiles16_kernel(int n, int ldS, int nb, const double* __restrict__ S, double scale,
+                                    _Float16* __restrict__ T) {
+  const long f = blockIdx.x;
+  int I = 0;
+  long rem = f;
+  while (rem >= nb - I) {
+    rem -= nb - I;
+    ++I;
+  }
+  const int J = I + (int)rem;
+  _Float16* tile = T + f * (long)(kTile * kTile);
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int r = e / kTile, c = e - r * kTile;
+    const int row = I * kTile + r, col = J * kTile + c;
+    tile[tile16_offset(r, c)] = (row < n && col < n) ? (_Float16)(S[(size_t)row * ldS + col] * scale) : (_Float16)0.0f;
+  }
+}
+
+void pack_tiles16_device(int n, int ldS, const double* S, double scale, uint16_t* T, hipStream_t stream) {
+  const int nb = (n + kTile - 1) / kTile;
+  hipLaunchKernelGGL(pack_tiles16_kernel, dim3((unsigned)tile_count(n)), dim3(256), 0, stream, n, ldS, nb, S, scale,
+                     reinterpret_cast<_Float16*>(T));
+}
+
 void to_float_device(size_t cnt, const double* a, float* b, hipStream_t stream) {
   hipLaunchKernelGGL(to_float_kernel, dim3(1024), dim3(256), 0, stream, cnt, a, b);
 }

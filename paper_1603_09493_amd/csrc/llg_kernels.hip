@@ -481,6 +481,8 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
   const int rg = lane >> 4, cq = lane & 15;
   const GLB float* Sg = reinterpret_cast<const GLB float*>(glb(g.S));
   const GLB float* Stg = g.St ? glb(g.St) : nullptr;      // packed tiles, when the group keeps them
+  const GLB uint4* St16g = !g.St && g.St16 ? reinterpret_cast<const GLB uint4*>(glb(g.St16)) : nullptr;
+  const float sinv = St16g ? g.s16_inv : 1.0f;           // FP16 tiles hold S times a power of two
   GLB float* __restrict__ ug = reinterpret_cast<GLB float*>(glb(g.u));
   const int NB = (n + 63) >> 6;
   const int ntile = NB * (NB + 1) / 2;
@@ -506,7 +508,19 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
       const int col0 = 64 * J + 4 * cq;
       const bool cok = col0 < ldS;   // ldS is a multiple of 4: the whole 16-byte word is in the row
       float4 sv[16];
-      if (Stg) {
+      if (St16g) {
+        // FP16 tile: load u of the wave reads the contiguous kilobyte u, two rows per lane
+        const GLB uint4* tile = St16g + (size_t)f * (kTile * kTile / 8);
+        typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint4 w = tile[(u * 4 + rg) * 16 + cq];
+          const half2v a0 = __builtin_bit_cast(half2v, w.x), a1 = __builtin_bit_cast(half2v, w.y);
+          const half2v b0 = __builtin_bit_cast(half2v, w.z), b1 = __builtin_bit_cast(half2v, w.w);
+          sv[2 * u] = make_float4((float)a0.x, (float)a0.y, (float)a1.x, (float)a1.y);
+          sv[2 * u + 1] = make_float4((float)b0.x, (float)b0.y, (float)b1.x, (float)b1.y);
+        }
+      } else if (Stg) {
         // packed tile: load t of the wave reads the contiguous kilobyte t (zero beyond n)
         const GLB float4* tile = reinterpret_cast<const GLB float4*>(Stg + (size_t)f * (kTile * kTile));
 #pragma unroll
@@ -536,7 +550,7 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
             h[j] = keep + __shfl_xor(send, m, 64);
           }
         }
-        if (64 * I + lane < n) atomicAdd(&uL[(size_t)r * ldS + 64 * I + lane], h[0]);
+        if (64 * I + lane < n) atomicAdd(&uL[(size_t)r * ldS + 64 * I + lane], h[0] * sinv);
         if (I < J) {
           // rows 16rg .. 16rg + 15 of b_I (row0 is a multiple of 16, as is ldS)
           float bi[16];
@@ -556,7 +570,7 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
           const float c0 = (g1 ? cp[2] : cp[0]) + __shfl_xor(g1 ? cp[0] : cp[2], 32, 64);
           const float c1 = (g1 ? cp[3] : cp[1]) + __shfl_xor(g1 ? cp[1] : cp[3], 32, 64);
           const float cs = (g0 ? c1 : c0) + __shfl_xor(g0 ? c0 : c1, 16, 64);
-          if (col0 + rg < n) atomicAdd(&uL[(size_t)r * ldS + col0 + rg], cs);
+          if (col0 + rg < n) atomicAdd(&uL[(size_t)r * ldS + col0 + rg], cs * sinv);
         }
       }
       // next tile of this wave: nw further along the flat index
@@ -1339,6 +1353,11 @@ __global__ __launch_bounds__(256) void energy_kernel(const GroupView<real>* __re
       double skl;
       if (g.S) {
         skl = (double)g.S[(size_t)k * g.ldS + l];
+      } else if (!g.St) {
+        const int a = min(k, l), b = max(k, l);
+        const _Float16 h = reinterpret_cast<const _Float16*>(g.St16)[(size_t)tile_index(nb, a / kTile, b / kTile) * (kTile * kTile) +
+                                                                    tile16_offset(a % kTile, b % kTile)];
+        skl = (double)h * (double)g.s16_inv;
       } else {
         const int a = min(k, l), b = max(k, l);
         skl = (double)g.St[(size_t)tile_index(nb, a / kTile, b / kTile) * (kTile * kTile) +

@@ -3,7 +3,8 @@ or compute at minimum), used to turn measured kernel times into roofline fractio
 
 Per mesh group with N nodes, nnz pattern entries, R instances, p bytes per real:
   demag operator S         p N^2                         (read once per evaluation; p N (N+1) / 2
-                                                          when only its upper triangle is read)
+                                                          when only its upper triangle is read;
+                                                          p = 2 for the FP16 tiles)
   CSR pattern + values     nnz (8 + 7 p)                 (col twice, K and D in phase A, DT in C)
   node constants           N (12 + 2 p)                  (rowptr, layer, partner, V, aif)
   per-instance vectors     R N p * 35.5                  (stage input twice, yex, b, u, the
@@ -19,8 +20,10 @@ MI355X_FP64_TFLOPS = 78.6
 MI355X_BF16_TFLOPS = 2500.0
 
 
-def eval_bytes(N: int, nnz: int, R: int, p: int, symmetric: bool = False) -> float:
-    s_bytes = p * N * (N + 1) / 2 if symmetric else p * N * N
+def eval_bytes(N: int, nnz: int, R: int, p: int, symmetric: bool = False, ps: int | None = None) -> float:
+    """ps: bytes per stored entry of S when it differs from p (FP16 tiles: 2)."""
+    ps = p if ps is None else ps
+    s_bytes = ps * N * (N + 1) / 2 if symmetric else ps * N * N
     return s_bytes + nnz * (8 + 7 * p) + N * (12 + 2 * p) + R * N * p * 35.5
 
 

@@ -49,14 +49,15 @@ def _batch_rows():
     return X, rows
 
 
-@pytest.mark.parametrize("keep", [3, 6, 4])
+@pytest.mark.parametrize("keep", [3, 6, 4, 8])
 def test_tiled_symmetric_product_against_oracle(ctx, oracle_mod, keep):
     """FP32 fixed-step DP5 (200 steps of 5 fs) of four batch islands in one launch, one workgroup
     each, upper-triangle demag product, from seeded states within 0.6 rad of +z: every node within
     1e-4 of the FP64 oracle, and within 2e-5 of the same launch with the full product.  keep 3:
     tiles read from the row-major S; 6: from the packed upper-triangle tiles; 4: the group keeps
     only the packed tiles (the full product is then refused), whose unpacked copy equals S to FP32
-    rounding."""
+    rounding; 8: only the FP16 tiles, whose unpacked copy is within FP16 rounding (2^-11
+    relative) of every entry."""
     from paper_1603_09493_amd import bpm
     X, rows = _batch_rows()
     T, dt = 1e-12, 5e-15
@@ -71,13 +72,18 @@ def test_tiled_symmetric_product_against_oracle(ctx, oracle_mod, keep):
             Sg = ctx.mesh_get_S(mid)
             assert np.array_equal(Sg, Sg.T)
             assert np.abs(Sg - S).max() <= 2 ** -23 * np.abs(S).max(), np.abs(Sg - S).max()
+        if keep == 8:
+            Sg = ctx.mesh_get_S(mid)
+            assert np.array_equal(Sg, Sg.T)
+            assert np.all(np.abs(Sg - S) <= 2 ** -11 * np.abs(S)), np.abs((Sg - S) / S).max()
+            assert np.abs(Sg - S).max() > 0.0
         m0 = I.random_unit_m(mesh.n, seed=100 + q, cone=0.6)
         cases.append((mesh, mat, fld, om, S, ctx.instance_add(mid, mat, fld, m0=m0), m0))
     _case("tiled-symmetric", keep=keep, sizes=[c[0].n for c in cases])
     assert min(c[0].n for c in cases) < 300 and max(c[0].n for c in cases) > 2800
     got, energy = {}, {}
     for name, flags in (("sym", bpm.FLAG_SYMMETRIC_DEMAG), ("full", 0)):
-        if keep == 4 and name == "full":
+        if keep in (4, 8) and name == "full":
             with pytest.raises(bpm.BpmError) as e:
                 ctx.run(t_end=T, precision=32, integrator=bpm.DP5_FIXED, dt_fixed=dt, wg_per_group=1, flags=flags)
             assert e.value.code == bpm.BPM_EINVAL
@@ -188,11 +194,12 @@ def test_continue_misuse_is_rejected(ctx):
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="tests/golden/cfg2_switching.json not generated")
-def test_batch_switching_parity_64_designs():
+@pytest.mark.parametrize("keep", ["KEEP_S32_TILES", "KEEP_S16_TILES"])
+def test_batch_switching_parity_64_designs(keep):
     """64 designs of the batch (266-2898 nodes) in one FP32 adaptive launch, one workgroup per
-    island, upper-triangle demag product on the packed tiles (the bench's storage), 0.3 ns: the switched flag agrees with the FP64 oracle
-    wherever the oracle's final hard-layer <m_z> is clear of zero, and the switching time and
-    field agree within 1 %."""
+    island, upper-triangle demag product on the packed FP32 tiles (the bench's storage) or on the
+    FP16 tiles, 0.3 ns: the switched flag agrees with the FP64 oracle wherever the oracle's final
+    hard-layer <m_z> is clear of zero, and the switching time and field agree within 1 %."""
     from paper_1603_09493_amd import bpm
     with open(GOLDEN) as f:
         gold = json.load(f)
@@ -203,8 +210,8 @@ def test_batch_switching_parity_64_designs():
         for d in gold["designs"]:
             mesh, mat, fld = I.design_inputs(X[d["row"]], seed=d["row"])
             assert mesh.n == d["n"]
-            ids.append(c.instance_add(c.mesh_add(mesh, keep=bpm.KEEP_S32_TILES), mat, fld))
-        _case("batch-64", sizes=f"{min(d['n'] for d in gold['designs'])}-{max(d['n'] for d in gold['designs'])}")
+            ids.append(c.instance_add(c.mesh_add(mesh, keep=getattr(bpm, keep)), mat, fld))
+        _case("batch-64", keep=keep, sizes=f"{min(d['n'] for d in gold['designs'])}-{max(d['n'] for d in gold['designs'])}")
         # one workgroup per island, as in the 4096-island launch (64 groups alone would get a
         # cooperative share of the GPU each)
         c.run(t_end=gold["t_end"], precision=32, rtol=1e-5, flags=bpm.FLAG_SYMMETRIC_DEMAG, wg_per_group=1)
