@@ -420,6 +420,39 @@ def rotation_chain(n: int, P: int, via=(1.0, 0.0, 0.0)) -> np.ndarray:
     return np.ascontiguousarray(np.repeat(d[:, :, None], n, axis=2))
 
 
+def lhs_maximin(n: int, d: int, seed: int = 0, sweeps: int = 200) -> np.ndarray:
+    """Seeded Latin hypercube of n points in [0, 1]^d with a larger smallest pairwise distance:
+    each coordinate takes one point in each of the n strata (at a uniform position inside it);
+    random swaps of two points' coordinate in one dimension are kept when they do not shrink the
+    smallest pairwise distance (the space-filling start of the global optimiser, Sec. II.A)."""
+    rng = np.random.default_rng(seed)
+    P = np.stack([rng.permutation(n) for _ in range(d)], axis=1)
+    U = (P + rng.random((n, d))) / n
+
+    def mindist(A):
+        D = np.sqrt(((A[:, None, :] - A[None, :, :]) ** 2).sum(-1))
+        D[np.arange(len(A)), np.arange(len(A))] = np.inf
+        return D.min()
+
+    best = mindist(U)
+    for _ in range(sweeps * n):
+        j = rng.integers(d)
+        a, b = rng.choice(n, 2, replace=False)
+        V = U.copy()
+        V[a, j], V[b, j] = U[b, j], U[a, j]
+        m = mindist(V)
+        if m >= best:
+            U, best = V, m
+    return U
+
+
+# Free media and placement parameters of the write-error optimisation (Table I without the head
+# geometry): K_1,hard (J/m^3), A_ex,int (J/m), down-track offset (m), cross-track offset (m).
+OPT_NAMES = ("K_hard", "A_int", "down_offset", "cross_offset")
+OPT_LO = np.array([0.5e6, 1e-12, 0.0, -8e-9])
+OPT_HI = np.array([1.2e6, 10e-12, 8e-9, 8e-9])
+
+
 # Design-vector layout used by the batched designs and the surrogate:
 DESIGN_NAMES = ("d", "t_soft", "t_hard", "Ms_soft", "Ms_hard", "K_soft", "K_hard", "A_int",
                 "psi", "B_peak", "alpha", "t_rise")
