@@ -278,6 +278,39 @@ int bpm_last_run_layout(bpm_ctx* ctx, int32_t* threads_per_wg, int32_t* s_rows_l
 int bpm_string_reparam(bpm_ctx* ctx, int32_t n_images, const int32_t* ids, double* arclen);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Global optimiser: expected improvement of a kriging model                                  */
+/* ------------------------------------------------------------------------------------------ */
+/* The paper's optimiser (efficient global optimisation, Sec. II.A) models the objective on the
+ * unit box as a constant mu plus a Gaussian process of variance sigma2 with correlation
+ * R(a, b) = exp(-sum_l theta_l (a_l - b_l)^2), fitted to the n designs evaluated so far, and
+ * evaluates next the design of largest expected improvement over the best value f_min.  With
+ * R = L L' the training correlation matrix (any nugget included), alpha = R^-1 (y - 1 mu),
+ * w = R^-1 1 and c = 1' w, the model at a candidate x with correlations r is
+ *   yhat = mu + alpha' r,  s^2 = sigma2 (1 - r' R^-1 r + (1 - w' r)^2 / c),
+ *   EI = (f_min - yhat) Phi(z) + s phi(z), z = (f_min - yhat) / s  (max(f_min - yhat, 0) if s = 0),
+ * with r' R^-1 r = |L^-1 r|^2.  All pointers below are device memory, FP64:
+ *   X [n][d] training points, theta [d], G [n + 2][n] = the rows of L^-1 (zeros above its
+ *   diagonal), then alpha', then w'.
+ * 1 <= d <= 16, n >= 1, c > 0, sigma2 >= 0.                                                    */
+typedef struct {
+  int32_t n, d;
+  double mu, sigma2, c, f_min;
+  const double* X;
+  const double* theta;
+  const double* G;
+} bpm_gp;
+
+/* EI (and, if non-NULL, yhat and s) at m candidates cand [m][d] in the unit box.  seed != 0:
+ * the call first fills cand with uniforms from Philox4x32-10, key (seed low, seed high), counter
+ * (index low, index high, l / 4, 0), word l mod 4, u = (w + 1/2) 2^-32 for coordinate l; seed = 0:
+ * cand is read.  Work is queued on hip_stream (NULL = the context's stream).                   */
+int bpm_gp_ei(bpm_ctx* ctx, const bpm_gp* gp, int64_t m, double* cand, uint64_t seed, double* yhat,
+              double* s, double* ei, void* hip_stream);
+/* Index of the largest of v [m] (device FP64, m >= 1), the lowest index among equal values (NaN
+ * never wins), into idx (device int64 [1]); queued on hip_stream (NULL = the context's stream). */
+int bpm_argmax(bpm_ctx* ctx, const double* v, int64_t m, int64_t* idx, void* hip_stream);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Learned screen                                                                             */
 /* ------------------------------------------------------------------------------------------ */
 /* The paper's optimizer proposes each new design from a Gaussian-process surrogate of the

@@ -54,6 +54,12 @@ class bpm_field(C.Structure):
                 ("g_origin", C.c_double * 3), ("g_h", C.c_double)]
 
 
+class bpm_gp(C.Structure):
+    _fields_ = [("n", C.c_int32), ("d", C.c_int32), ("mu", C.c_double), ("sigma2", C.c_double),
+                ("c", C.c_double), ("f_min", C.c_double), ("X", C.c_void_p), ("theta", C.c_void_p),
+                ("G", C.c_void_p)]
+
+
 class bpm_run_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("integrator", C.c_int32), ("t_end", C.c_double),
                 ("dt0", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
@@ -83,7 +89,7 @@ SYMBOLS = [
 EXTRA_SYMBOLS = [
     "bpm_mlp_num_params", "bpm_mlp_create", "bpm_mlp_destroy", "bpm_mlp_set_params", "bpm_mlp_get_params",
     "bpm_mlp_predict", "bpm_mlp_grads", "bpm_mlp_train_step", "bpm_sample_designs", "bpm_topk", "bpm_screen",
-    "bpm_topk_noalloc",
+    "bpm_topk_noalloc", "bpm_gp_ei", "bpm_argmax",
 ]
 
 _lib = None
@@ -125,6 +131,8 @@ def lib():
     L.bpm_get_trajectory.argtypes = [P, I32, P, I64, C.POINTER(I64)]
     L.bpm_get_m.argtypes = [P, I32, P, I32]
     L.bpm_string_reparam.argtypes = [P, I32, P, P]
+    L.bpm_gp_ei.argtypes = [P, C.POINTER(bpm_gp), I64, P, C.c_uint64, P, P, P, P]
+    L.bpm_argmax.argtypes = [P, P, I64, P, P]
     L.bpm_last_run_info.argtypes = [P, C.POINTER(D), C.POINTER(I32), C.POINTER(I32)]
     L.bpm_last_run_layout.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]
     L.bpm_mlp_num_params.argtypes = []
@@ -441,6 +449,21 @@ def topk_noalloc(ctx: Context, score, k, idx, n=None, stream=None):
     n = score.shape[0] if n is None else n
     with _ts(stream) as st:
         ctx._check(ctx.L.bpm_topk_noalloc(ctx.h, _dp(score), int(n), int(k), _dp(idx), st))
+
+
+def gp_ei(ctx: Context, model: bpm_gp, m, cand, ei, seed=0, yhat=None, sd=None, stream=None):
+    """bpm_gp_ei on device tensors: EI (and yhat, s) of the kriging model at m candidates
+    (generated into cand when seed != 0)."""
+    with _ts(stream) as st:
+        ctx._check(ctx.L.bpm_gp_ei(ctx.h, C.byref(model), int(m), _dp(cand), C.c_uint64(int(seed)),
+                                   None if yhat is None else _dp(yhat), None if sd is None else _dp(sd), _dp(ei), st))
+
+
+def argmax(ctx: Context, v, idx, m=None, stream=None):
+    """bpm_argmax: index of the largest of the device FP64 values v into the device int64 idx."""
+    m = v.shape[0] if m is None else m
+    with _ts(stream) as st:
+        ctx._check(ctx.L.bpm_argmax(ctx.h, _dp(v), int(m), _dp(idx), st))
 
 
 def sample_designs(ctx: Context, seed, n, X, stream=None):

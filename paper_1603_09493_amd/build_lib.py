@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libbpmllg.so")
 ARCH = os.environ.get("BPM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["assembly.cpp", "abi.cpp", "demag.hip", "llg_kernels.hip", "heun.hip", "mlp.hip",
-           "screen.hip", "string.hip"]
+           "screen.hip", "string.hip", "gp.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          # packed FP32 instructions are kept out of the generated code

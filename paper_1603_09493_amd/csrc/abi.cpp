@@ -30,6 +30,10 @@ void pack_tiles16_device(int n, int ldS, const double* S, double scale, uint16_t
 hipError_t extract_m_device(int precision, long n, long rstride, long offset, const void* src, double* dst,
                             hipStream_t stream);
 void symmetrize_device(int n, int ldS, double* S, hipStream_t stream);
+hipError_t gp_ei_device(const GpArgs& a, long m, double* cand, uint64_t seed, double* yhat, double* sd, double* ei,
+                        hipStream_t stream);
+int argmax_blocks(long m);
+hipError_t argmax_device(const double* v, long m, double* bv, long* bi, int64_t* out, hipStream_t stream);
 hipError_t string_reparam_device(int precision, long n, int P, const StringImages& im, double* d_dist,
                                  double* d_out, hipStream_t stream);
 
@@ -1382,6 +1386,38 @@ int bpm_string_reparam(bpm_ctx* c, int32_t P, const int32_t* ids, double* arclen
     arclen[0] = 0.0;
     for (int k = 1; k < P; ++k) arclen[k] = arclen[k - 1] + h_d[k - 1];
   }
+  return BPM_OK;
+}
+
+int bpm_gp_ei(bpm_ctx* c, const bpm_gp* gp, int64_t m, double* cand, uint64_t seed, double* yhat, double* s,
+              double* ei, void* hip_stream) {
+  if (!c) return BPM_EINVAL;
+  if (!gp || !ei || !cand || m < 0) return fail(c, BPM_EINVAL, "bpm_gp_ei: null argument or negative count");
+  if (gp->d < 1 || gp->d > kMaxGpDim || gp->n < 1 || !gp->X || !gp->theta || !gp->G)
+    return fail(c, BPM_EINVAL, "bpm_gp_ei: need 1 <= d <= 16, n >= 1 and the model arrays");
+  if (!(gp->c > 0.0) || !(gp->sigma2 >= 0.0) || !std::isfinite(gp->mu) || !std::isfinite(gp->f_min))
+    return fail(c, BPM_EINVAL, "bpm_gp_ei: need c > 0, sigma2 >= 0 and finite mu, f_min");
+  HIPCHK(c, hipSetDevice(c->device));
+  GpArgs a{gp->n, gp->d, gp->mu, gp->sigma2, gp->c, gp->f_min, gp->X, gp->theta, gp->G};
+  hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->own_stream;
+  HIPCHK(c, gp_ei_device(a, (long)m, cand, seed, yhat, s, ei, st));
+  return BPM_OK;
+}
+
+int bpm_argmax(bpm_ctx* c, const double* v, int64_t m, int64_t* idx, void* hip_stream) {
+  if (!c) return BPM_EINVAL;
+  if (!v || !idx || m < 1) return fail(c, BPM_EINVAL, "bpm_argmax: need m >= 1 and device arrays");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->own_stream;
+  const int nb = argmax_blocks((long)m);
+  double* bv = nullptr;
+  long* bi = nullptr;
+  HIPCHK(c, hipMallocAsync(reinterpret_cast<void**>(&bv), sizeof(double) * nb, st));
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&bi), sizeof(long) * nb, st);
+  if (e == hipSuccess) e = argmax_device(v, (long)m, bv, bi, idx, st);
+  hipFreeAsync(bv, st);
+  if (bi) hipFreeAsync(bi, st);
+  HIPCHK(c, e);
   return BPM_OK;
 }
 

@@ -68,6 +68,16 @@ constexpr int kMaxSysPerGroup = 64;   // adaptive-control state is replicated in
 constexpr int kMaxInstPerGroup = 64;
 constexpr int kStringMaxImages = 64;   // images of one string (bpm_string_reparam)
 
+// Kriging model of the optimiser, as the expected-improvement kernel reads it (device pointers).
+constexpr int kMaxGpDim = 16;
+struct GpArgs {
+  int32_t n, d;
+  double mu, sigma2, c, f_min;
+  const double* X;       // [n][d]
+  const double* theta;   // [d]
+  const double* G;       // [n + 2][n]: L^-1 (zeros above the diagonal), alpha', w'
+};
+
 // Device pointers of the images of one string, in chain order (a kernel argument).
 struct StringImages {
   const void* p[kStringMaxImages];

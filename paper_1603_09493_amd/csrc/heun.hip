@@ -19,24 +19,13 @@
 #include "bpm_internal.h"
 #include "heun_internal.h"
 #include "field_eval.h"
+#include "philox.h"
 
 namespace bpm {
 
-__device__ __forceinline__ uint4 philox_10(uint4 c, uint2 k) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-    k.x += 0x9E3779B9u;
-    k.y += 0xBB67AE85u;
-  }
-  return c;
-}
-
 // three standard normals for (key, step, node)
 __device__ __forceinline__ void gauss3(uint2 key, unsigned long long step, uint32_t node, double g[3]) {
-  const uint4 w = philox_10(make_uint4((uint32_t)step, (uint32_t)(step >> 32), node, 0u), key);
+  const uint4 w = philox4x32_10(make_uint4((uint32_t)step, (uint32_t)(step >> 32), node, 0u), key);
   const double s = 1.0 / 4294967296.0;
   const double u0 = ((double)w.x + 0.5) * s, u1 = ((double)w.y + 0.5) * s;
   const double u2 = ((double)w.z + 0.5) * s, u3 = ((double)w.w + 0.5) * s;
@@ -50,7 +39,7 @@ __device__ __forceinline__ void gauss3(uint2 key, unsigned long long step, uint3
 
 // the same three normals with the transforms in FP32 (FP32 runs; the words are the same)
 __device__ __forceinline__ void gauss3(uint2 key, unsigned long long step, uint32_t node, float g[3]) {
-  const uint4 w = philox_10(make_uint4((uint32_t)step, (uint32_t)(step >> 32), node, 0u), key);
+  const uint4 w = philox4x32_10(make_uint4((uint32_t)step, (uint32_t)(step >> 32), node, 0u), key);
   const float s = 2.3283064365386963e-10f;   // 2^-32
   const float u0 = ((float)w.x + 0.5f) * s, u1 = ((float)w.y + 0.5f) * s;
   const float u2 = ((float)w.z + 0.5f) * s, u3 = ((float)w.w + 0.5f) * s;

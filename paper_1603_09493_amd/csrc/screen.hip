@@ -10,24 +10,9 @@
 #include <mutex>
 
 #include "mlp_internal.h"
+#include "philox.h"
 
 namespace bpm {
-
-// ---------------------------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 multiply-xor bijection with the
-// Weyl key schedule
-// ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-    k.x += 0x9E3779B9u;
-    k.y += 0xBB67AE85u;
-  }
-  return c;
-}
 
 // X[i][f] = 2 u - 1 with u = (x + 1/2) 2^-32 from Philox(key = seed, counter = (i, call)), three
 // calls per design give the 12 uniforms in order.
