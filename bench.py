@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 T_PROCESS = time.time()
 METRIC = "island-ns simulated/s (batched LLG) + surrogate designs/s at ≤2% Hsw error"
-COUNTERS = os.path.join(ROOT, "profiles", "dp5_kernel_cfg2_batch_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "dp5_kernel_batch4096_%stiles_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1603_09493_amd", "csrc", "llg_kernels.hip")
 
 
@@ -72,7 +72,7 @@ def traffic_ratio(storage="fp32"):
     """(FETCH_SIZE + WRITE_SIZE) of the profiled stepping launch, scaled by the counters' reading
     for a device copy of known size, per algorithmic byte of that launch -- or None when the
     summary is missing or was taken on another kernel source or storage of S."""
-    path = COUNTERS if storage == "fp32" else COUNTERS.replace("_batch_", "_batch_%s_" % storage)
+    path = COUNTERS % storage
     if not os.path.exists(path):
         return None
     kv = {}
@@ -82,7 +82,7 @@ def traffic_ratio(storage="fp32"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     try:
-        if kv["kernel_source_sha256"] != kernel_source_sha():
+        if kv["kernel_source_sha256"] != kernel_source_sha() or kv.get("demag_storage", storage) != storage:
             return None
         fetch = float(kv["fetch_kib_per_launch"]) * 1024 * float(kv["fetch_scale"])
         write = float(kv["write_kib_per_launch"]) * 1024 * float(kv["write_scale"])
@@ -193,6 +193,43 @@ def surrogate_leg(ctx, rows, res, n_test=512, n_cand=1_000_000, k=10_000, epochs
             "valid_at_2pct": bool(head.size and head.mean() <= 0.02)}
 
 
+def ego_ei_leg(ctx, n=128, d=4, m=1 << 22, reps=5):
+    """Expected improvement of a fitted kriging model (n training points in d dimensions) at m
+    Philox candidates per call, and its argmax: the GPU step of the global optimiser.  Algorithmic
+    FP64 work per candidate: the n correlations (3d + 2 flops each, the exponential counted as
+    one), the triangular L^-1 r (n (n + 1) flops), alpha' r and w' r (4n), the n squares (2n) and
+    about 40 for the EI formula."""
+    import numpy as np
+    import torch
+    from paper_1603_09493_amd import bpm as B, ego, roofline
+    from paper_1603_09493_amd import inputs as I
+    X = I.lhs_maximin(n, d, seed=5, sweeps=5)
+    y = np.sin(5 * X[:, 0]) * np.cos(3 * X[:, 1]) + (X ** 2).sum(1)
+    t0 = time.perf_counter()
+    model = ego.fit(X, y, starts=4)
+    fit_s = time.perf_counter() - t0
+    prop = ego.Proposer(ctx, d, m)
+    idx = torch.empty(1, dtype=torch.int64, device="cuda")
+    dm = prop.evaluate(model, float(y.min()), 1)
+    torch.cuda.synchronize()
+    # a stream of its own, so that the events bracket exactly the library's launches on it
+    st = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(st)
+    for r in range(reps):
+        B.gp_ei(ctx, dm.desc, m, prop.cand, prop.ei, seed=2 + r, yhat=prop.yhat, sd=prop.sd, stream=st.cuda_stream)
+        B.argmax(ctx, prop.ei, idx, stream=st.cuda_stream)
+    ev[1].record(st)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    flops = m * (n * (3 * d + 2) + n * (n + 1) + 6 * n + 40)
+    del dm
+    return {"n_train": n, "d": d, "candidates": m, "ms_per_call": ms, "candidates_per_s": m / ms * 1e3,
+            "fit_s": fit_s, "bound": "alu", "achieved_tflops": flops / ms / 1e9,
+            "peak_tflops": roofline.MI355X_FP64_TFLOPS, "frac": flops / ms / 1e9 / roofline.MI355X_FP64_TFLOPS,
+            "kernel": "gp_ei_kernel + argmax (FP64 vector FMA; peak: FP64 78.6 TFLOP/s)"}
+
+
 def thermal_leg(ctx, meshes, realizations=1024, steps=40, dt=5e-15, temperature=300.0):
     """Thermal-erasure workload: each mesh (the patch island, one mesh seed per design) carries
     `realizations` Philox streams of the single-island material in a static stray field drawn
@@ -253,6 +290,7 @@ def main():
                     help="wall-clock budget of the whole process; stepping stops early to keep it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-ego", action="store_true", help="skip the optimiser's EI kernel leg")
     ap.add_argument("--full-demag", action="store_true", help="read all of S (default: its upper triangle)")
     ap.add_argument("--demag-storage", choices=["fp32", "fp16"], default="fp32",
                     help="storage of the packed upper-triangle tiles of S (arithmetic stays FP32)")
@@ -424,6 +462,13 @@ def main():
                                                     if solver_rate else None)
         except Exception as e:   # the line is still printed
             out["surrogate"] = {"error": repr(e)}
+    if not args.no_ego:
+        try:
+            out["ego_ei"] = ego_ei_leg(ctx)
+            log(f"ego EI: {out['ego_ei']['candidates_per_s']:.3g} candidates/s, "
+                f"{out['ego_ei']['achieved_tflops']:.2f} TFLOP/s FP64")
+        except Exception as e:
+            out["ego_ei"] = {"error": repr(e)}
     if args.thermal > 0:
         try:
             out["thermal"] = thermal_leg(ctx, thermal_meshes, steps=args.thermal_steps)

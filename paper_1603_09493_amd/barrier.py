@@ -61,13 +61,17 @@ def profile_barrier(s, E) -> float:
 
 def string_barrier(ctx: bpm.Context, mid: int, n: int, mat, fld, chain, offset=(0.0, 0.0, 0.0),
                    dtau: float = 2e-12, iters: int = 60, precision: int = 64, rtol: float | None = None,
-                   wg_per_group: int = 0) -> Barrier:
+                   wg_per_group: int = 0, relax_alpha: float | None = 1.0) -> Barrier:
     """Simplified string method from `chain` ([P][3][n] initial images, e.g.
-    inputs.rotation_chain) for one island on mesh group `mid` in the static field `fld`."""
+    inputs.rotation_chain) for one island on mesh group `mid` in the static field `fld`.  The
+    relaxation runs use damping relax_alpha (the energy landscape does not depend on it; None
+    keeps the material's)."""
     chain = np.asarray(chain, dtype=np.float64)
     P = chain.shape[0]
     if rtol is None:
         rtol = 1e-6 if precision == 64 else 1e-5
+    if relax_alpha is not None:
+        mat = dataclasses.replace(mat, alpha=float(relax_alpha))
     ctx.clear_instances()
     ids = [ctx.instance_add(mid, mat, fld, offset=offset, m0=chain[k]) for k in range(P)]
     hist, ms = [], 0.0
@@ -102,3 +106,55 @@ def adjacent_error(ctx: bpm.Context, mesh, mid: int, mat, grid, g_origin, g_h, l
     b = string_barrier(ctx, mid, mesh.n, mat, fld, I.rotation_chain(mesh.n, P), offset=layout["adjacent"],
                        dtau=dtau, iters=iters, precision=precision)
     return ber_adj(b.E_B, T=T), b
+
+
+def string_barrier_many(ctx: bpm.Context, mesh, mats, flds, chains, offsets, dtau: float = 2e-12, iters: int = 60,
+                        precision: int = 64, rtol: float | None = None, relax_alpha: float | None = 1.0,
+                        mids: list | None = None) -> list:
+    """string_barrier for many strings of one island mesh in lock step: every iteration relaxes
+    all images of all strings in one launch (64 // P strings per copy of the mesh group), then
+    redistributes each string."""
+    from .ber_driver import group_slots
+    q = len(mats)
+    chains = [np.asarray(c, dtype=np.float64) for c in chains]
+    P = chains[0].shape[0]
+    if rtol is None:
+        rtol = 1e-6 if precision == 64 else 1e-5
+    mids = [] if mids is None else mids
+    groups = group_slots(ctx, mesh, mids, q, P)
+    ctx.clear_instances()
+    ids = []
+    for k in range(q):
+        m = mats[k] if relax_alpha is None else dataclasses.replace(mats[k], alpha=float(relax_alpha))
+        ids.append([ctx.instance_add(groups[k], m, flds[k], offset=tuple(offsets[k]), m0=chains[k][j]) for j in range(P)])
+    hist = [[] for _ in range(q)]
+    ms = 0.0
+    E = [None] * q
+    s = [None] * q
+    for _ in range(iters):
+        ctx.run(t_end=dtau, precision=precision, rtol=rtol, flags=bpm.FLAG_RELAX)
+        ctx.sync()
+        ms += ctx.last_run_info()["kernel_ms"]
+        res = ctx.results([i for row in ids for i in row])
+        bad = [r["status"] for r in res if r["status"] != 0]
+        if bad:
+            raise RuntimeError(f"string relaxation failed: statuses {bad[:8]}")
+        for k in range(q):
+            E[k] = np.array([r["energy"] for r in res[k * P:(k + 1) * P]])
+            s[k] = ctx.string_reparam(ids[k])
+            hist[k].append(profile_barrier(s[k], E[k]))
+    n = mesh.n
+    return [Barrier(hist[k][-1], E[k], s[k], [ctx.get_m(i, n) for i in ids[k]], hist[k], ms) for k in range(q)]
+
+
+def adjacent_errors_many(ctx: bpm.Context, mesh, mats, grid, g_origin, g_h, cross_offsets, layout=None,
+                         P: int = 16, iters: int = 60, dtau: float = 2e-12, precision: int = 64, T: float = 300.0,
+                         mids: list | None = None):
+    """adjacent_error for many designs (materials and cross-track offsets) in lock step:
+    returns [(BER_adj, Barrier)]."""
+    layout = I.recording_layout() if layout is None else layout
+    flds = [I.adjacent_field(grid, g_origin, g_h, layout=layout, cross_offset=c) for c in cross_offsets]
+    chains = [I.rotation_chain(mesh.n, P)] * len(mats)
+    bs = string_barrier_many(ctx, mesh, mats, flds, chains, [layout["adjacent"]] * len(mats), dtau=dtau,
+                             iters=iters, precision=precision, mids=mids)
+    return [(ber_adj(b.E_B, T=T), b) for b in bs]

@@ -167,3 +167,30 @@ def test_write_errors_abort_when_head_is_too_weak(oracle_mod):
     assert len(w.targ.levels) == 1 and not w.targ.levels[0][1].any()
     _, ro, _ = om.run(S, [mat], [fld], dict(t_end=I.BIT_PERIOD, rtol=1e-6))
     assert ro[0]["switched"] == 0
+
+
+def test_lock_step_write_errors_match_single_design_runs(rec, oracle_mod):
+    """Three designs (K_1,hard, down-track offset) through write_errors_many in lock step, FP64:
+    stage and both brackets as in three write_errors runs (to one refined grid step, since the
+    instance packing differs between the launches), and fewer launches than the three in a row."""
+    from paper_1603_09493_amd import ber_driver as D, bpm
+    mesh, om, S, mat0, (g, org, h) = rec
+    lay = I.recording_layout()
+    designs = [(I.media_material(K_hard=K), I.recording_field(g, org, h, down_offset=dn))
+               for K, dn in ((0.8e6, 4e-9), (1.2e6, 6.8e-9), (0.6e6, 2e-9))]
+    ctx = bpm.Context(0)
+    try:
+        mid = ctx.mesh_add(mesh, S)
+        print(f"[gpu-case] write-errors-single x{len(designs)}", flush=True)
+        singles = [D.write_errors(ctx, mesh, mid, m, f, layout=lay, precision=64) for m, f in designs]
+        print("[gpu-case] write-errors-many", flush=True)
+        many = D.write_errors_many(ctx, mesh, designs, layout=lay, precision=64, mids=[mid])
+    finally:
+        ctx.close()
+    for a, b in zip(singles, many):
+        assert a.stage == b.stage
+        step = 0.5 * a.targ.sigma / 169 * 1.01
+        assert abs(a.targ.h_crit - b.targ.h_crit) <= step
+        if a.prev is not None and b.prev is not None:
+            assert abs(a.prev.h_crit - b.prev.h_crit) <= step
+    print("[ber-many] stages", [w.stage for w in many], "BER_tot", [w.ber_tot for w in many], flush=True)

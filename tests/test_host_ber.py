@@ -25,6 +25,10 @@ class ThresholdCtx:
     def clear_instances(self):
         self.inst = []
 
+    def mesh_add(self, mesh, keep=3):
+        self.meshes = getattr(self, "meshes", 0) + 1
+        return self.meshes - 1
+
     def instance_add(self, mid, mat, fld, offset=None):
         self.inst.append((fld, tuple(offset)))
         return len(self.inst) - 1
@@ -134,3 +138,39 @@ def test_recording_layout_is_pseudo_hexagonal():
     ff = math.pi * 6e-9 ** 2 / (13.5e-9 * 11.7e-9)
     assert abs(ff - 0.716) < 0.001
     assert abs(I.BIT_PERIOD - 1e-9) < 1e-21
+
+
+def test_lock_step_searches_match_the_single_design_driver():
+    """write_errors_many over designs whose head strengths differ gives, design by design, the
+    result of write_errors, in as many launches as the longest single search needs."""
+    lay = {"target": (0.0, 0.0, 0.0), "previous": (-1.0, 0.0, 0.0), "adjacent": (0.5, 1.0, 0.0)}
+    mesh = I.media_mesh(n_target=300)
+    strengths = [(1.0 + m * SIG, 1.0 - p * SIG) for m, p in ((0.3, 4.0), (-0.5, 3.0), (2.26, 12.0),
+                                                             (4.1, -0.5), (9.7, 7.7), (17.0, 2.0), (1.1, 30.0))]
+    singles = []
+    for st, sp in strengths:
+        ctx = ThresholdCtx({(0.0, 0.0, 0.0): st, (-1.0, 0.0, 0.0): sp})
+        singles.append(D.write_errors(ctx, mesh, 0, MAT, FLD, layout=lay))
+
+    class Multi(ThresholdCtx):
+        """each design's field carries its own head strength in B_peak (uniform field)"""
+        def results(self, ids):
+            out = []
+            for i in ids:
+                fld, off = self.inst[i]
+                d = D.head_direction(fld, off, 1e-9)
+                h = float(np.dot(np.asarray(fld.B_ext), d))
+                out.append({"status": 0, "switched": int(fld.B_peak[off == (0.0, 0.0, 0.0)] + h > self.hsw)})
+            return out
+
+    import dataclasses
+    designs = [(MAT, dataclasses.replace(FLD, B_peak=(sp, st))) for st, sp in strengths]
+    ctx = Multi({})
+    many = D.write_errors_many(ctx, mesh, designs, layout=lay)
+    for a, b in zip(singles, many):
+        assert a.stage == b.stage and a.ber_tot == b.ber_tot and a.ber_targ == b.ber_targ
+        if a.prev is not None:
+            assert a.prev.lo == b.prev.lo and a.prev.hi == b.prev.hi
+    longest = max(len(w.targ.levels) for w in singles) + max(len(w.prev.levels) for w in singles if w.prev)
+    assert len(ctx.calls) == longest
+    assert max(ctx.calls) == 12 * len(designs)
