@@ -36,7 +36,8 @@ def sigma_T(K_hard: float, Ms_hard: float) -> float:
 
 
 def ber_from_hcrit(h: float, sigma: float) -> float:
-    return 0.5 * (1.0 - math.erf(h / math.sqrt(2.0 * sigma * sigma)))
+    """Eqs. (1)-(2), written with erfc so that rates far in the tail keep their digits."""
+    return 0.5 * math.erfc(h / math.sqrt(2.0 * sigma * sigma))
 
 
 @dataclasses.dataclass

@@ -9,8 +9,9 @@
 //   EI = (f_min - yhat) Phi(z) + s phi(z),  z = (f_min - yhat) / s.
 // For a block of 64 candidates that product is a 64 x n by n x (n + 2) matrix product: 256
 // threads hold 4 candidates x 4 rows of G each, the correlations are formed while a 16-column
-// slice of them is staged in LDS, and only the lower triangle of L^-1 is visited.  FP64
-// throughout (the variance is a difference of nearly equal terms near training points).
+// slice of them is staged in LDS, and only the lower triangle of L^-1 is visited; two row tiles
+// share each staged slice, and alpha' r and w' r are summed while the correlations are formed.
+// FP64 throughout (the variance is a difference of nearly equal terms near training points).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,14 +27,17 @@ namespace {
 constexpr int kGpBS = 256;
 constexpr int kGpC = 64;      // candidates per block
 constexpr int kGpK = 16;      // columns of G per LDS stage
+constexpr int kGpTiles = 2;   // 64-row tiles of L^-1 per pass over the correlations
+static_assert(kGpBS == 4 * kGpC, "four threads form the correlations of each candidate");
 
 __global__ __launch_bounds__(kGpBS) void gp_ei_kernel(GpArgs a, long m, double* __restrict__ cand,
                                                       uint64_t seed, double* __restrict__ yhat,
                                                       double* __restrict__ sd, double* __restrict__ ei) {
   __shared__ double xc[kGpC][kMaxGpDim];
   __shared__ double Rt[kGpK][kGpC + 1];
-  __shared__ double Gt[kGpC][kGpK + 1];
+  __shared__ double Gt[kGpTiles][kGpC][kGpK + 1];
   __shared__ double th[kMaxGpDim];
+  __shared__ double red[2][kGpBS];
   const int t = threadIdx.x;
   const long c0 = (long)blockIdx.x * kGpC;
   const int d = a.d, n = a.n;
@@ -57,15 +61,21 @@ __global__ __launch_bounds__(kGpBS) void gp_ei_kernel(GpArgs a, long m, double* 
     xc[cc][l] = x;
   }
   const int cs = t >> 4, rs = t & 15;    // candidates 4 cs .. 4 cs + 3, rows 4 rs .. 4 rs + 3 of a tile
-  double qa[4] = {0, 0, 0, 0}, ya[4] = {0, 0, 0, 0}, pa[4] = {0, 0, 0, 0};
-  const int NR = n + 2;
-  for (int i0 = 0; i0 < NR; i0 += kGpC) {
-    // rows below n are rows of the lower-triangular L^-1: columns beyond the tile's last row are zero
-    const int kmax = i0 + kGpC <= n ? i0 + kGpC : n;
-    double acc[4][4] = {};
+  const int ccr = t & (kGpC - 1);        // the candidate whose correlations this thread forms
+  const double* alpha = a.G + (size_t)n * n;
+  const double* wv = a.G + (size_t)(n + 1) * n;
+  double qa[4] = {0, 0, 0, 0};
+  double ya = 0.0, pa = 0.0;             // alpha' r and w' r of candidate ccr, partial over its j
+  const int nt = (n + kGpC - 1) / kGpC;  // 64-row tiles of L^-1
+  for (int p0 = 0; p0 < nt; p0 += kGpTiles) {
+    const int p1 = min(p0 + kGpTiles, nt);
+    const bool last = p1 == nt;
+    // rows of L^-1 below 64 p1 have no entries beyond column 64 p1 - 1; the last pass also forms
+    // alpha' r and w' r, so it covers every column
+    const int kmax = last ? n : kGpC * p1;
+    double acc[kGpTiles][4][4] = {};
     for (int j0 = 0; j0 < kmax; j0 += kGpK) {
       __syncthreads();
-      // correlations of the 64 candidates with training points j0 .. j0 + 15
       for (int e = t; e < kGpK * kGpC; e += kGpBS) {
         const int jj = e / kGpC, cc = e - jj * kGpC;
         const int j = j0 + jj;
@@ -77,55 +87,66 @@ __global__ __launch_bounds__(kGpBS) void gp_ei_kernel(GpArgs a, long m, double* 
             s += th[l] * u * u;
           }
           r = exp(-s);
+          if (last) {
+            ya = fma(alpha[j], r, ya);
+            pa = fma(wv[j], r, pa);
+          }
         }
         Rt[jj][cc] = r;
       }
-      for (int e = t; e < kGpC * kGpK; e += kGpBS) {
-        const int ii = e / kGpK, jj = e - ii * kGpK;
-        const int i = i0 + ii, j = j0 + jj;
-        Gt[ii][jj] = (i < NR && j < n) ? a.G[(size_t)i * n + j] : 0.0;
+      for (int e = t; e < (p1 - p0) * kGpC * kGpK; e += kGpBS) {
+        const int tl = e / (kGpC * kGpK), rem = e - tl * (kGpC * kGpK);
+        const int ii = rem / kGpK, jj = rem - ii * kGpK;
+        const int i = kGpC * (p0 + tl) + ii, j = j0 + jj;
+        Gt[tl][ii][jj] = (i < n && j < n) ? a.G[(size_t)i * n + j] : 0.0;
       }
       __syncthreads();
+#pragma unroll
+      for (int tl = 0; tl < kGpTiles; ++tl) {
+        if (p0 + tl >= p1 || j0 >= kGpC * (p0 + tl + 1)) continue;   // beyond this tile's triangle
 #pragma unroll 4
-      for (int jj = 0; jj < kGpK; ++jj) {
-        double rv[4], gv[4];
+        for (int jj = 0; jj < kGpK; ++jj) {
+          double rv[4], gv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rv[u] = Rt[jj][4 * cs + u];
+          for (int u = 0; u < 4; ++u) rv[u] = Rt[jj][4 * cs + u];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) gv[u] = Gt[4 * rs + u][jj];
+          for (int u = 0; u < 4; ++u) gv[u] = Gt[tl][4 * rs + u][jj];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = fma(rv[u], gv[v], acc[u][v]);
+            for (int v = 0; v < 4; ++v) acc[tl][u][v] = fma(rv[u], gv[v], acc[tl][u][v]);
+        }
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + 4 * rs + v;
+    for (int tl = 0; tl < kGpTiles; ++tl)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (i < n) qa[u] = fma(acc[u][v], acc[u][v], qa[u]);
-        else if (i == n) ya[u] += acc[u][v];
-        else if (i == n + 1) pa[u] += acc[u][v];
+      for (int v = 0; v < 4; ++v) {
+        const int i = kGpC * (p0 + tl) + 4 * rs + v;
+        if (p0 + tl < p1 && i < n)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) qa[u] = fma(acc[tl][u][v], acc[tl][u][v], qa[u]);
       }
-    }
   }
-  // sums over the 16 threads (rs) that share a candidate quartet: lanes 16 cs .. 16 cs + 15
+  // |L^-1 r|^2: sums over the 16 threads (rs) that share a candidate quartet (lanes 16 cs ..)
 #pragma unroll
   for (int w = 8; w >= 1; w >>= 1)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      qa[u] += __shfl_xor(qa[u], w, 16);
-      ya[u] += __shfl_xor(ya[u], w, 16);
-      pa[u] += __shfl_xor(pa[u], w, 16);
-    }
+    for (int u = 0; u < 4; ++u) qa[u] += __shfl_xor(qa[u], w, 16);
+  // alpha' r and w' r: sums over the four threads that formed correlations of one candidate
+  red[0][t] = ya;
+  red[1][t] = pa;
+  __syncthreads();
   if (rs == 0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const long c = c0 + 4 * cs + u;
+      const int cl = 4 * cs + u;
+      const long c = c0 + cl;
       if (c >= m) continue;
-      const double mu = a.mu + ya[u];
-      const double one_p = 1.0 - pa[u];
+      const double yv = red[0][cl] + red[0][cl + 64] + red[0][cl + 128] + red[0][cl + 192];
+      const double pv = red[1][cl] + red[1][cl + 64] + red[1][cl + 128] + red[1][cl + 192];
+      const double mu = a.mu + yv;
+      const double one_p = 1.0 - pv;
       const double var = a.sigma2 * (1.0 - qa[u] + one_p * one_p / a.c);
       const double s = var > 0.0 ? sqrt(var) : 0.0;
       const double imp = a.f_min - mu;

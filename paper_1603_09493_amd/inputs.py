@@ -376,8 +376,8 @@ def write_head_grid(B_peak: float, dir, L_grad: float, W_pole: float, P_len: flo
     return g, tuple(float(v) for v in lo), float(h)
 
 
-def default_head_grid(B_peak: float = 1.6, psi_deg: float = 25.0):
-    """The synthetic head used by the write-error driver: 1.6 T peak, tilted psi from -z toward
+def default_head_grid(B_peak: float = 2.2, psi_deg: float = 25.0):
+    """The synthetic head used by the write-error driver: 2.2 T peak, tilted psi from -z toward
     +x, 10 nm pole length and width, 4 nm edge length, 25 nm decay below the soft-layer top,
     sampled over [-40, 50] x [-30, 30] x [-2.5, 15] nm."""
     psi = math.radians(psi_deg)
