@@ -158,16 +158,60 @@ class Proposer:
         return out
 
 
+def propose_batch(prop: Proposer, X, y, model: Model, q: int, seed: int):
+    """q points for one parallel evaluation (the kriging believer): after each pick of the
+    largest EI the model's prediction there is added as if observed (same correlation
+    parameters) and EI is evaluated again, so the next pick looks elsewhere."""
+    Xb, yb = np.array(X), np.array(y)
+    f_min = float(y.min())
+    picks = []
+    for k in range(q):
+        mk = model if k == 0 else model_arrays(Xb, yb, model.theta, mu=model.mu, sigma2=model.sigma2)
+        x, e, yh, s = prop.propose(mk, f_min, seed * 1000 + k)
+        picks.append((x, e, yh, s))
+        Xb = np.vstack([Xb, x])
+        yb = np.append(yb, yh)
+    return picks
+
+
 def optimise(ctx: bpm.Context, f, X0, iters: int, m: int = 1 << 18, seed: int = 1, ei_tol: float = 0.0,
-             log=None, f_many=None) -> dict:
+             log=None, f_many=None, q: int = 1) -> dict:
     """The loop of Sec. II.A: evaluate the start points, then fit, propose the largest-EI
     candidate, evaluate it, until iters points were added or the largest EI is <= ei_tol.
-    f_many (optional) evaluates a list of points at once (the start design in one batch)."""
+    f_many (optional) evaluates a list of points at once (the start design in one batch, and,
+    with q > 1, q kriging-believer proposals per step)."""
     X = np.array(X0, dtype=np.float64)
     t0 = time.perf_counter()
     y = np.array(f_many(list(X)) if f_many is not None else [f(x) for x in X], dtype=np.float64)
     prop = Proposer(ctx, X.shape[1], m)
     hist = dict(ei=[], fit_s=0.0, ei_s=0.0, judge_s=0.0, start_s=time.perf_counter() - t0, stopped="iterations")
+    if q > 1:
+        if f_many is None:
+            raise ValueError("q > 1 needs f_many")
+        added, it = 0, 0
+        while added < iters:
+            t0 = time.perf_counter()
+            model = fit(X, y, seed=it)
+            t1 = time.perf_counter()
+            picks = propose_batch(prop, X, y, model, min(q, iters - added), seed + it)
+            t2 = time.perf_counter()
+            hist["fit_s"] += t1 - t0
+            hist["ei_s"] += t2 - t1
+            hist["ei"].append(picks[0][1])
+            if picks[0][1] <= ei_tol:
+                hist["stopped"] = "expected improvement %.3g <= %.3g" % (picks[0][1], ei_tol)
+                break
+            xs = [p[0] for p in picks]
+            fx = f_many(xs)
+            hist["judge_s"] += time.perf_counter() - t2
+            X = np.vstack([X] + [x[None] for x in xs])
+            y = np.append(y, fx)
+            added += len(xs)
+            it += 1
+            if log:
+                log(f"ego batch {it}: {len(xs)} points, EI {picks[0][1]:.3g} -> best {y.min():.4f}")
+        hist.update(X=X, y=y, best=int(np.argmin(y)))
+        return hist
     for it in range(iters):
         t0 = time.perf_counter()
         model = fit(X, y, seed=it)
@@ -272,6 +316,7 @@ def main(argv=None):
     ap.add_argument("--candidates", type=int, default=1 << 18)
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1, help="kriging-believer points judged together per step")
     a = ap.parse_args(argv)
     import sys
     log = lambda s: print(s, file=sys.stderr, flush=True)
@@ -285,12 +330,13 @@ def main(argv=None):
         fm = ber_objective_many(ctx, mesh, grid, precision=a.precision, details=det)
         t0 = time.perf_counter()
         X0 = I.lhs_maximin(a.start, 4, seed=a.seed)
-        h = optimise(ctx, f, X0, a.steps, m=a.candidates, seed=a.seed, log=log, f_many=fm)
+        h = optimise(ctx, f, X0, a.steps, m=a.candidates, seed=a.seed, log=log, f_many=fm, q=a.batch)
         wall = time.perf_counter() - t0
     finally:
         ctx.close()
     k = h["best"]
-    print(json.dumps({"start_designs": a.start, "ei_steps": len(h["ei"]), "nodes": mesh.n, "precision": a.precision,
+    print(json.dumps({"start_designs": a.start, "ei_steps": len(h["ei"]), "batch": a.batch,
+                      "evaluations": int(len(h["y"])), "nodes": mesh.n, "precision": a.precision,
                       "start_s": h["start_s"], "start_designs_per_s": a.start / h["start_s"],
                       "fit_s": h["fit_s"], "ei_s": h["ei_s"], "judge_s": h["judge_s"], "wall_s": wall,
                       "best_log10_ber": float(h["y"][k]), "best_design": unit_to_design(h["X"][k]).tolist(),

@@ -111,3 +111,18 @@ def test_ego_with_write_error_judge():
             assert r["ber_tot"] == 1.0 and r["ber_adj"] is None
         else:
             assert r["ber_adj"] is not None and r["E_B"] > 0
+
+
+def test_ego_batch_steps_find_branin_minimum():
+    """Four kriging-believer points per step, judged together: the same Branin bar within the
+    same number of evaluations, in a quarter of the steps."""
+    from paper_1603_09493_amd import bpm, ego
+    ctx = bpm.Context(0)
+    try:
+        print("[gpu-case] ego-branin-batch", flush=True)
+        h = ego.optimise(ctx, _branin, I.lhs_maximin(10, 2, seed=3), iters=28, m=1 << 16, q=4,
+                         f_many=lambda xs: [_branin(x) for x in xs])
+    finally:
+        ctx.close()
+    assert len(h["y"]) == 38 and len(h["ei"]) == 7
+    assert h["y"].min() < 0.397887 + 0.05, h["y"].min()
