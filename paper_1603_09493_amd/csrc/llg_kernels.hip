@@ -74,6 +74,28 @@ __device__ __forceinline__ double dpp_add(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RM, 0xF, false);
   return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
+// v of the partner lane in halving step M (8, 4, 2, 1) of a butterfly inside each 16-lane row:
+// row rotation by 8, half-row mirror, quad permutes [3,2,1,0] and [1,0,3,2].  The partners of
+// step M differ in bit log2 M of the lane index and agree in every higher bit, so four steps
+// pair every lane of the row with every other exactly once, and a lane can keep the half of
+// its values selected by its own bit, as with xor partners; no LDS traffic.
+template <int M>
+__device__ __forceinline__ float row_step_partner(float v) {
+  constexpr int ctrl = M == 8 ? 0x128 : M == 4 ? 0x141 : M == 2 ? 0x1B : 0xB1;
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+}
+
+// h[0..2M) of each lane -> h[0..M): the half picked by the lane's bit M, plus the partner's
+template <int M>
+__device__ __forceinline__ void row_halve(float* h, bool up) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const float keep = up ? h[j + M] : h[j];
+    const float send = up ? h[j] : h[j + M];
+    h[j] = keep + row_step_partner<M>(send);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum_to63(T v) {
   v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
@@ -466,14 +488,16 @@ __device__ __forceinline__ void phase_B(const GroupView<real>& g, Ctl& c, int i0
 // loads in flight per lane) and forms
 //   row sums     u_I += S_IJ b_J                   (every tile, the diagonal tile in full), and
 //   column sums  u_J += S_IJ^T b_I = S_JI b_I      (tiles above the diagonal).
-// Row sums are reduced over the 16 lanes of a row group and column sums over the four row groups
-// by halving exchanges, so that each lane ends with one row (64I + lane) and one column
-// (64J + 4cq + rg), which it adds into u in LDS (uL, RB x ldS after bL).  The order of those LDS
-// additions, and with it the rounding of u, varies from run to run.  Tiles go round-robin over
-// the waves of the workgroup.  The tiles come from the packed copy when the group keeps it (each
+// Row sums are reduced over the 16 lanes of a row group (a DPP butterfly inside the row, see
+// row_halve) and column sums over the four row groups by halving exchanges, so that each lane
+// ends with one row (64I + lane) and one column (64J + 4cq + rg), which it adds into u in LDS
+// (uL, RB x ldS after bL).  The order of those LDS additions, and with it the rounding of u,
+// varies from run to run.  When every instance of the group fits in one block of right-hand
+// sides, u stays in LDS for phase C (the pointer returned; nothing is written to global memory),
+// else it is copied out block by block.  Tiles go round-robin over the waves of the workgroup.  The tiles come from the packed copy when the group keeps it (each
 // load instruction of a wave then reads one contiguous kilobyte), else from the row-major S.
 template <typename real, int BS>
-__device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, real* bL, int RB) {
+__device__ __forceinline__ const real* phase_B_sym(const GroupView<real>& g, Ctl& c, real* bL, int RB) {
   static_assert(sizeof(real) == 4, "the tiled symmetric product is the FP32 path");
   const int n = g.n, ldS = g.ldS;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -500,31 +524,61 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
                           rn * ldS / 4);
     for (int idx = threadIdx.x; idx < rn * ldS; idx += BS) uL[idx] = 0.f;
     __syncthreads();
-    // tile (I, J) of flat upper-triangle index f = wid, wid + nw, ... (row-major over I <= J)
+    // tile (I, J) of flat upper-triangle index f = wid, wid + nw, ... (row-major over I <= J).
+    // With packed tiles the wave loads the first half of its next tile (FP16: all of it) into
+    // `pre` while it works on the current one, so that half a tile of loads stays in flight
+    // during the arithmetic (a whole FP32 tile there would spill registers).
     int I = 0, J = wid;
     while (J >= NB && I < NB) { J -= NB - I - 1; ++I; }
+    constexpr int kPre = 8;
+    float4 pre[kPre];
     for (int f = wid; f < ntile; f += nw) {
       const int row0 = 64 * I + 16 * rg;
       const int col0 = 64 * J + 4 * cq;
       const bool cok = col0 < ldS;   // ldS is a multiple of 4: the whole 16-byte word is in the row
       float4 sv[16];
       if (St16g) {
-        // FP16 tile: load u of the wave reads the contiguous kilobyte u, two rows per lane
+        // FP16 tile: load u of the wave reads the contiguous kilobyte u, two rows per lane; the
+        // whole tile was loaded during the previous tile's product
         const GLB uint4* tile = St16g + (size_t)f * (kTile * kTile / 8);
         typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+        if (f == wid) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pre[u] = __builtin_bit_cast(float4, tile[(u * 4 + rg) * 16 + cq]);
+        }
+        uint4 cw[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cw[u] = __builtin_bit_cast(uint4, pre[u]);
+        if (f + nw < ntile) {
+          const GLB uint4* nt = tile + (size_t)nw * (kTile * kTile / 8);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pre[u] = __builtin_bit_cast(float4, nt[(u * 4 + rg) * 16 + cq]);
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const uint4 w = tile[(u * 4 + rg) * 16 + cq];
+          const uint4 w = cw[u];
           const half2v a0 = __builtin_bit_cast(half2v, w.x), a1 = __builtin_bit_cast(half2v, w.y);
           const half2v b0 = __builtin_bit_cast(half2v, w.z), b1 = __builtin_bit_cast(half2v, w.w);
           sv[2 * u] = make_float4((float)a0.x, (float)a0.y, (float)a1.x, (float)a1.y);
           sv[2 * u + 1] = make_float4((float)b0.x, (float)b0.y, (float)b1.x, (float)b1.y);
         }
       } else if (Stg) {
-        // packed tile: load t of the wave reads the contiguous kilobyte t (zero beyond n)
+        // packed tile: load t of the wave reads the contiguous kilobyte t (zero beyond n); the
+        // first half of each tile was loaded during the previous tile's product
         const GLB float4* tile = reinterpret_cast<const GLB float4*>(Stg + (size_t)f * (kTile * kTile));
+        if (f == wid) {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) sv[t] = tile[(t * 4 + rg) * 16 + cq];
+          for (int t = 0; t < kPre; ++t) pre[t] = tile[(t * 4 + rg) * 16 + cq];
+        }
+#pragma unroll
+        for (int t = kPre; t < 16; ++t) sv[t] = tile[(t * 4 + rg) * 16 + cq];
+#pragma unroll
+        for (int t = 0; t < kPre; ++t) sv[t] = pre[t];
+        if (f + nw < ntile) {
+          const GLB float4* nt = tile + (size_t)nw * (kTile * kTile / 4);
+#pragma unroll
+          for (int t = 0; t < kPre; ++t) pre[t] = nt[(t * 4 + rg) * 16 + cq];
+        }
       } else {
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
@@ -540,16 +594,10 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
         float h[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) h[t] = sv[t].x * bj.x + sv[t].y * bj.y + sv[t].z * bj.z + sv[t].w * bj.w;
-#pragma unroll
-        for (int m = 8; m >= 1; m >>= 1) {
-          const bool up = cq & m;
-#pragma unroll
-          for (int j = 0; j < m; ++j) {
-            const float keep = up ? h[j + m] : h[j];
-            const float send = up ? h[j] : h[j + m];
-            h[j] = keep + __shfl_xor(send, m, 64);
-          }
-        }
+        row_halve<8>(h, cq & 8);
+        row_halve<4>(h, cq & 4);
+        row_halve<2>(h, cq & 2);
+        row_halve<1>(h, cq & 1);
         if (64 * I + lane < n) atomicAdd(&uL[(size_t)r * ldS + 64 * I + lane], h[0] * sinv);
         if (I < J) {
           // rows 16rg .. 16rg + 15 of b_I (row0 is a multiple of 16, as is ldS)
@@ -578,11 +626,13 @@ __device__ __forceinline__ void phase_B_sym(const GroupView<real>& g, Ctl& c, re
       while (J >= NB && I < NB) { J -= NB - I - 1; ++I; }
     }
     __syncthreads();
+    if (g.R <= RB) return reinterpret_cast<const real*>(uL);   // phase C reads u from LDS
     for (int idx = threadIdx.x; idx < rn * n; idx += BS) {
       const int r = idx / n, l = idx - r * n;
       ug[(size_t)(rb + r) * ldS + l] = uL[(size_t)r * ldS + l];
     }
   }
+  return nullptr;
 }
 
 // Dipole moments of coupled instances, mu_I = sum_i Ms_L(i) V_i y_i of a stage input y: every
@@ -651,7 +701,7 @@ __device__ __forceinline__ void dipole_fields(Ctl& c, const InstConst* icL, cons
 template <typename real, bool kL, bool kX>
 __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst& ic,
                                        int s, int r, int k, int i0, int sl, const GLB real* __restrict__ ysrc,
-                                       GLB real* __restrict__ ydst, const Csr<real, kL>& cs) {
+                                       GLB real* __restrict__ ydst, const Csr<real, kL>& cs, const real* uL) {
   const int nk = s < 6 ? s : 6;     // earlier stages read
   const int n = g.n, ldS = g.ldS, i = i0 + k;
   const size_t st3 = (size_t)3 * n;
@@ -682,10 +732,16 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
   real dx = 0, dy = 0, dz = 0;
   const int qa = cs.rp[k], qb = cs.rp[k + 1];
   constexpr int kGather = Gather<real, kX>::W;
+  const real* uLr = uL ? uL + (size_t)r * ldS : nullptr;
   for (int q0 = qa; q0 < qb; q0 += kGather) {
     real uq[kGather];
+    if (uLr) {
 #pragma unroll
-    for (int w = 0; w < kGather; ++w) uq[w] = xld<kX>(u + (q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i));
+      for (int w = 0; w < kGather; ++w) uq[w] = uLr[q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i];
+    } else {
+#pragma unroll
+      for (int w = 0; w < kGather; ++w) uq[w] = xld<kX>(u + (q0 + w < qb ? (cs.col[q0 + w] & 0xFFFF) : i));
+    }
 #pragma unroll
     for (int w = 0; w < kGather; ++w) {
       const int q = q0 + w;
@@ -787,7 +843,7 @@ __device__ __forceinline__ void pair_C(const GroupView<real>& g, const RunParams
 template <typename real, bool kFixed, int BS, bool kL, bool kX>
 __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParams& P, Ctl& c, const InstConst* icL,
                                         const double* dipL, int i0, int i1, int s, const real* ysrc_, real* ydst_,
-                                        int it, int ev, const Csr<real, kL>& cs) {
+                                        int it, int ev, const Csr<real, kL>& cs, const real* uL) {
   const int nown = i1 - i0;
   const GLB real* ysrc = glb(ysrc_);
   GLB real* ydst = glb(ydst_);
@@ -803,7 +859,7 @@ __device__ __forceinline__ void phase_C(const GroupView<real>& g, const RunParam
     const int r = it2 / nown, k = it2 - r * nown;
     const int sl = c.isys[r];
     if (!c.active[sl]) continue;
-    pair_C<real, kL, kX>(g, P, c, icL[r], s, r, k, i0, sl, ysrc, ydst, cs);
+    pair_C<real, kL, kX>(g, P, c, icL[r], s, r, k, i0, sl, ysrc, ydst, cs, uL);
   }
   if (c.any_coupled && s >= 1 && s < 6) {
     __syncthreads();
@@ -844,9 +900,10 @@ __device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunPa
   double mv = 0.0;
   if (mq) mv = acc_ld(&P.mom_acc[((size_t)(g.inst0 + threadIdx.x / 3) * 3 + ev % 3) * 3 + threadIdx.x % 3]);
   bool done = false;
+  const real* uL = nullptr;
   if constexpr (!kX && sizeof(real) == 4) {
     if (!SL && g.G == 1 && (P.flags & BPM_FLAG_SYMMETRIC_DEMAG)) {
-      phase_B_sym<real, BS>(g, c, bL, RB);
+      uL = phase_B_sym<real, BS>(g, c, bL, RB);
       done = true;
     }
   }
@@ -860,7 +917,7 @@ __device__ __forceinline__ void field_eval(const GroupView<real>& g, const RunPa
     dipole_fields<BS>(c, icL, dipL, g.R);
   }
   group_sync<kX>(gs);
-  phase_C<real, kFixed, BS, kL, kX>(g, P, c, icL, dipL, i0, i1, s, ysrc, ydst, it, ev, cs);
+  phase_C<real, kFixed, BS, kL, kX>(g, P, c, icL, dipL, i0, i1, s, ysrc, ydst, it, ev, cs, uL);
   group_sync<kX>(gs);
 }
 
