@@ -16,7 +16,8 @@
  *     bit decides writing success.  The stochastic LLG (thermal field) of the attempt-frequency
  *     calculation in Sec. II.C is the Heun integrator below.
  * Everything the paper leaves open (time integrator, error norm, demag operator, switching
- * criterion, thermal-field variance, random numbers) follows the readings listed in the design doc.
+ * criterion, thermal-field variance, random numbers) follows one stated reading, given in the
+ * comment of the function that implements it.
  *
  * Precision: IEEE double throughout.  Parallelism: OpenMP across independent systems only.
  */

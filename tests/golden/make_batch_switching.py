@@ -1,4 +1,4 @@
-"""Writes cfg2_switching.json: FP64 oracle results for 64 designs of the batched-island workload.
+"""Writes batch4096_switching.json: FP64 oracle results for 64 designs of the batched-island workload.
 
 The designs are rows of the 4096-design batch (inputs.sample_designs(4096, seed=2)), picked to
 span the node counts (every 64th row in size order, the largest included), each meshed with its
@@ -7,7 +7,7 @@ adaptive Dormand-Prince 5(4) (FP64, rtol = atol = 1e-6) from m = +z to 0.3 ns an
 switched flag, the switching time and field and the final hard-layer <m_z>.  Only the oracle and
 the seeded input generator are used.
 
-Usage: python tests/golden/make_cfg2_switching.py [threads]
+Usage: python tests/golden/make_batch_switching.py [threads]
 """
 import concurrent.futures as cf
 import json
@@ -61,10 +61,10 @@ def main():
         for k in ("t_sw", "B_sw"):
             if r[k] != r[k]:
                 r[k] = None
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg2_switching.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch4096_switching.json")
     with open(path, "w") as f:
         json.dump({"t_end": T_END, "rtol": 1e-6, "designs": out,
-                   "source": "tests/golden/make_cfg2_switching.py (FP64 oracle)"}, f, indent=1)
+                   "source": "tests/golden/make_batch_switching.py (FP64 oracle)"}, f, indent=1)
     print("wrote", path)
 
 

@@ -7,7 +7,7 @@ continued runs, through the C ABI.
 * Continued runs (BPM_FLAG_CONTINUE) against one run: identical for fixed steps on their grid,
   the same switching for adaptive steps; misuse rejected.
 * 64 designs of the 4096-island batch, FP32 adaptive in one launch, against the FP64 oracle's
-  switching time and field (stored by tests/golden/make_cfg2_switching.py, which calls only the
+  switching time and field (stored by tests/golden/make_batch_switching.py, which calls only the
   oracle).
 """
 import json
@@ -21,7 +21,7 @@ from paper_1603_09493_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_switching.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch4096_switching.json")
 
 
 @pytest.fixture(scope="module")
@@ -193,7 +193,7 @@ def test_continue_misuse_is_rejected(ctx):
     assert e.value.code == bpm.BPM_ESTATE
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="tests/golden/cfg2_switching.json not generated")
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="tests/golden/batch4096_switching.json not generated")
 @pytest.mark.parametrize("keep", ["KEEP_S32_TILES", "KEEP_S16_TILES"])
 def test_batch_switching_parity_64_designs(keep):
     """64 designs of the batch (266-2898 nodes) in one FP32 adaptive launch, one workgroup per

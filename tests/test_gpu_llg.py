@@ -24,7 +24,7 @@ def ctx():
 
 
 @pytest.fixture(scope="module")
-def cfg0(oracle_mod):
+def single(oracle_mod):
     mesh, mat, fld = I.single_island_workload()
     om = oracle_mod.OracleMesh(mesh)
     S = om.demag_S()
@@ -39,8 +39,8 @@ def _print_case(name, **kw):
 # assembly and demag operator
 # ------------------------------------------------------------------------------------------
 
-def test_assembly_matches_oracle(ctx, cfg0):
-    mesh, mat, fld, om, S = cfg0
+def test_assembly_matches_oracle(ctx, single):
+    mesh, mat, fld, om, S = single
     _print_case("assembly", n=mesh.n)
     mid = ctx.mesh_add(mesh, S)
     a = ctx.mesh_get_assembly(mid)
@@ -55,8 +55,8 @@ def test_assembly_matches_oracle(ctx, cfg0):
     assert np.abs(a["aif"] - aif).max() <= 1e-12 * aif.max()
 
 
-def test_demag_operator_matches_oracle(ctx, cfg0, oracle_mod):
-    mesh, mat, fld, om, S = cfg0
+def test_demag_operator_matches_oracle(ctx, single, oracle_mod):
+    mesh, mat, fld, om, S = single
     _print_case("demag-S", n=mesh.n)
     mid = ctx.mesh_add(mesh)      # assembled on the GPU
     Sg = ctx.mesh_get_S(mid)
@@ -104,11 +104,11 @@ def _run_gpu(ctx, mesh, S, mats, flds, *, offsets=None, coupled=False, m0=None, 
 
 @pytest.mark.parametrize("wg,threads,s_in_lds", [(1, 256, False), (4, 256, False), (48, 256, True),
                                                   (48, 512, True), (48, 256, False)])
-def test_fp64_fixed_step_trajectory_parity(ctx, cfg0, oracle_mod, wg, threads, s_in_lds):
+def test_fp64_fixed_step_trajectory_parity(ctx, single, oracle_mod, wg, threads, s_in_lds):
     """The single-island workload (1.2 T at 30 degrees, 0.1 ns ramp), DP5 at dt = 10 fs; one
     workgroup, a few, and 48 workgroups whose rows of S stay in LDS (or are streamed)."""
     from paper_1603_09493_amd import bpm
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     T, dt = 0.05e-9, 10e-15
     flags = (bpm.FLAG_WG512 if threads == 512 else 0) | (0 if s_in_lds else bpm.FLAG_STREAM_S)
     _print_case("fp64-fixed", n=mesh.n, wg=wg, threads=threads, s_in_lds=s_in_lds, steps=int(T / dt))
@@ -128,12 +128,12 @@ def test_fp64_fixed_step_trajectory_parity(ctx, cfg0, oracle_mod, wg, threads, s
     assert abs(rg[0]["energy"] - ro[0]["energy"]) <= 1e-9 * abs(ro[0]["energy"])
 
 
-def test_fp64_fixed_step_parity_full_window(ctx, cfg0, oracle_mod):
+def test_fp64_fixed_step_parity_full_window(ctx, single, oracle_mod):
     """The single-island workload over its whole 0.3 ns (30000 steps of 10 fs, through the ramp
     and the reversal of the soft layer): every node within 1e-9 of the oracle.  The oracle run
     against itself from m0 + 1e-15 noise stays far below that bar over this window
     (tests/golden/parity_floor.txt)."""
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     T, dt = 0.3e-9, 10e-15
     _case_floor = open(__file__.rsplit("/", 1)[0] + "/golden/parity_floor.txt").read().split("\n")
     floor = max(float(l.split()[1]) for l in _case_floor if l and not l.startswith("#"))
@@ -146,9 +146,9 @@ def test_fp64_fixed_step_parity_full_window(ctx, cfg0, oracle_mod):
     assert abs(rg[0]["mz_soft"] - ro[0]["mz_soft"]) <= 1e-9
 
 
-def test_fp64_adaptive_parity(ctx, cfg0, oracle_mod):
+def test_fp64_adaptive_parity(ctx, single, oracle_mod):
     """rtol 1e-6 adaptive run of the single-island workload over 0.1 ns: same step sequence."""
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     T = 0.1e-9
     _print_case("fp64-adaptive", n=mesh.n)
     mo, ro, to = om.run(S, [mat], [fld], dict(t_end=T, rtol=1e-6), traj_cap=0)
@@ -160,10 +160,10 @@ def test_fp64_adaptive_parity(ctx, cfg0, oracle_mod):
 
 
 @pytest.mark.parametrize("B", [1.8, 2.0])
-def test_fp32_adaptive_switching_parity(ctx, cfg0, oracle_mod, B):
+def test_fp32_adaptive_switching_parity(ctx, single, oracle_mod, B):
     """FP32 adaptive (rtol = atol = 1e-5) vs the FP64 oracle (rtol 1e-6): switching time and
     field within 1 %."""
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     fl = dataclasses.replace(fld, B_peak=B)
     T = 0.2e-9
     _print_case("fp32-switch", n=mesh.n, B=B)
@@ -243,9 +243,9 @@ def test_fp32_full_patch_resident_and_streamed_S_agree(ctx):
 # per-instance failure handling
 # ------------------------------------------------------------------------------------------
 
-def test_failed_instance_does_not_stop_others(ctx, cfg0):
+def test_failed_instance_does_not_stop_others(ctx, single):
     from paper_1603_09493_amd import bpm
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     ctx.clear_instances()
     mid = ctx.mesh_add(mesh, S)
     good = ctx.instance_add(mid, mat, fld)
@@ -259,9 +259,9 @@ def test_failed_instance_does_not_stop_others(ctx, cfg0):
     assert rb["status"] == bpm.BPM_ENONFINITE
 
 
-def test_step_budget_and_underflow(ctx, cfg0):
+def test_step_budget_and_underflow(ctx, single):
     from paper_1603_09493_amd import bpm
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     ctx.clear_instances()
     mid = ctx.mesh_add(mesh, S)
     i = ctx.instance_add(mid, mat, fld)
@@ -274,9 +274,9 @@ def test_step_budget_and_underflow(ctx, cfg0):
     assert ctx.results([i])[0]["status"] == bpm.BPM_ESTEPUNDERFLOW
 
 
-def test_bad_arguments_are_rejected(ctx, cfg0):
+def test_bad_arguments_are_rejected(ctx, single):
     from paper_1603_09493_amd import bpm
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     with pytest.raises(bpm.BpmError):
         ctx.run(t_end=-1.0)
     bad = dataclasses.replace(mat, Ms=(0.0, 1e6))
@@ -289,11 +289,11 @@ def test_bad_arguments_are_rejected(ctx, cfg0):
         ctx.mesh_add(broken, None)
 
 
-def test_symmetric_demag_product_matches_full(ctx, cfg0, oracle_mod):
+def test_symmetric_demag_product_matches_full(ctx, single, oracle_mod):
     """FP32 with the upper-triangle demag product (one workgroup per group) against the full
     product and the FP64 oracle."""
     from paper_1603_09493_amd import bpm
-    mesh, mat, fld, om, S = cfg0
+    mesh, mat, fld, om, S = single
     fl = dataclasses.replace(fld, B_peak=1.8)
     T = 0.2e-9
     _print_case("fp32-symmetric", n=mesh.n)
