@@ -214,3 +214,21 @@ def screen_round(net: bpm.Mlp, seed: int, n: int, k: int, min_stability: float):
     dt = time.perf_counter() - t0
     picks = X[idx].cpu().numpy()
     return picks, dt, sc[idx].cpu().numpy()
+
+
+def active_round(ctx: bpm.Context, net: bpm.Mlp, sc: TargetScaler, X: np.ndarray, T: np.ndarray, mask: np.ndarray,
+                 seed: int, n: int, k: int, min_stability: float, t_end: float = 0.3e-9, epochs: int = 60,
+                 lr: float = 5e-4, progress=None):
+    """One closed round of the screen: score n candidates on the GPU, let the batched solver judge
+    the k best, append the judged designs to the training set and continue training on it.
+    Returns (X, T, mask) of the grown training set, the judged designs' Labels, their scaled
+    inputs and the screen time."""
+    picks, secs, _ = screen_round(net, seed=seed, n=n, k=k, min_stability=min_stability)
+    lab = label_designs(ctx, unscale(picks), t_end=t_end, progress=progress)
+    ok = lab.status == 0
+    Tn, mn = sc.targets(Labels(lab.switched[ok], lab.B_sw[ok], lab.t_sw[ok], lab.status[ok], 0, 0))
+    X2 = np.concatenate([X, picks[ok]]).astype(np.float32)
+    T2 = np.concatenate([T, Tn]).astype(np.float32)
+    m2 = np.concatenate([mask, mn])
+    train(net, X2, T2, m2, epochs=epochs, batch=64, lr=lr, seed=seed)
+    return X2, T2, m2, lab, picks, secs

@@ -1,6 +1,7 @@
 """The learned screen end to end, on the GPU: solver-labelled designs, training with the
-library's BF16 kernels, held-out switching-field error, and the gain of a screening round over
-random proposals (every pick re-verified by the batched solver, which stays the judge)."""
+library's BF16 kernels, held-out switching-field error, the gain of a screening round over
+random proposals (every pick re-verified by the batched solver, which stays the judge), and a
+second round after the judged picks joined the training set."""
 import numpy as np
 import pytest
 
@@ -66,5 +67,21 @@ def test_surrogate_trains_and_screens_better_than_random():
     print(f"[surrogate] screen 200k in {secs*1e3:.1f} ms; solver-verified switching: picks {hit_p:.2f} "
           f"vs random {hit_r:.2f}", flush=True)
     assert hit_p >= 0.75 and hit_p >= hit_r + 0.1
+    # closing the loop: the judged picks join the training set, training continues, and the next
+    # round's picks are judged again
+    _case("surrogate-active-round")
+    X1 = np.concatenate([X[tr], picks]).astype(np.float32)
+    T1p, m1p = sc.targets(lab_p)
+    T1 = np.concatenate([T, T1p]).astype(np.float32)
+    m1 = np.concatenate([mask, m1p])
+    train_n = X1.shape[0]
+    X2, T2, m2, lab2, picks2, secs2 = SG.active_round(ctx, net, sc, X1, T1, m1, seed=100, n=200_000, k=64,
+                                                       min_stability=min_stab, t_end=t_end, progress=_progress)
+    assert X2.shape[0] == train_n + 64 and T2.shape == (train_n + 64, 3)
+    hit2 = lab2.switched.mean()
+    print(f"[surrogate] round 2 after retraining on {train_n} + 64 designs: solver-verified switching "
+          f"{hit2:.2f}", flush=True)
+    assert hit2 >= 0.75
+    assert np.all(SG.stability(SG.unscale(picks2)) >= min_stab)
     net.close()
     ctx.close()
