@@ -17,8 +17,10 @@ early rather than overrun --budget-s, and the line says how much was simulated.
 
 Also reported: the roofline of the stepping kernel (algorithmic bytes / its HIP-event time), HBM
 traffic from the committed rocprofv3 counter summary, the learned screen (trained on the batch's
-own solver labels, held-out switching-field error, 1M-candidate screening rounds), and the FP64
-oracle on a subsample of the same designs on the host cores.
+own solver labels, held-out switching-field error, 1M-candidate screening rounds), the
+optimiser's expected-improvement kernel, the write-error evaluation (BER_tot of 16 designs in lock
+step), the stochastic path, and the FP64 oracle on a subsample of the same designs on the host
+cores.  --demag-storage fp16 runs the headline on FP16 tiles of S.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -230,6 +232,28 @@ def ego_ei_leg(ctx, n=128, d=4, m=1 << 22, reps=5):
             "kernel": "gp_ei_kernel + argmax (FP64 vector FMA; peak: FP64 78.6 TFLOP/s)"}
 
 
+def write_error_leg(ctx, designs=16, nodes=300):
+    """BER_tot of `designs` start designs of the optimiser (maximin Latin hypercube over K_1,hard,
+    A_ex,int and the down- and cross-track offsets, seed 1) on the synthetic 2.2 T head, FP32,
+    judged in lock step: the critical-field searches of the target and previous bit (12 fields
+    per level on a sigma/2 grid, two refinements) and the adjacent island's string (13 images,
+    30 iterations) of every design share launches."""
+    from paper_1603_09493_amd import ego
+    from paper_1603_09493_amd import inputs as I
+    mesh = I.media_mesh(n_target=nodes)
+    det = []
+    f = ego.ber_objective_many(ctx, mesh, I.default_head_grid(), precision=32, details=det)
+    U = I.lhs_maximin(designs, 4, seed=1)
+    t0 = time.perf_counter()
+    y = f(list(U))
+    dt = time.perf_counter() - t0
+    stages = [d["stage"] for d in det]
+    return {"designs": designs, "nodes": mesh.n, "precision": "f32", "wall_s": dt, "designs_per_s": designs / dt,
+            "stages": {k: stages.count(k) for k in sorted(set(stages))}, "best_log10_ber_tot": float(min(y)),
+            "search": "12 fields per level, sigma/2 grid, up to 4 extensions, 2 refinements, 1 ns write period",
+            "barrier": "string method, 13 images, 30 relaxation launches of 2 ps"}
+
+
 def thermal_leg(ctx, meshes, realizations=1024, steps=40, dt=5e-15, temperature=300.0):
     """Thermal-erasure workload: each mesh (the patch island, one mesh seed per design) carries
     `realizations` Philox streams of the single-island material in a static stray field drawn
@@ -291,6 +315,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-ego", action="store_true", help="skip the optimiser's EI kernel leg")
+    ap.add_argument("--no-ber", action="store_true", help="skip the write-error (BER_tot) leg")
     ap.add_argument("--full-demag", action="store_true", help="read all of S (default: its upper triangle)")
     ap.add_argument("--demag-storage", choices=["fp32", "fp16"], default="fp32",
                     help="storage of the packed upper-triangle tiles of S (arithmetic stays FP32)")
@@ -427,9 +452,9 @@ def main():
 
     signal.signal(signal.SIGTERM, on_term)
     # wall time kept for what follows the timed steps (measured: surrogate ~10 s, thermal leg
-    # ~3 s, oracle sample ~15 s), with margin
+    # ~3 s, oracle sample ~15 s, write-error leg ~20 s), with margin
     reserve = (20.0 + (0.0 if args.no_surrogate else 25.0) + (0.0 if args.no_cpu_baseline else 30.0)
-               + (0.0 if args.thermal <= 0 else 10.0 + 0.1 * args.thermal))
+               + (0.0 if args.thermal <= 0 else 10.0 + 0.1 * args.thermal) + (0.0 if args.no_ber else 40.0))
     stop = None
     t_step = None
     for k in range(args.steps):
@@ -469,6 +494,12 @@ def main():
                 f"{out['ego_ei']['achieved_tflops']:.2f} TFLOP/s FP64")
         except Exception as e:
             out["ego_ei"] = {"error": repr(e)}
+    if not args.no_ber:
+        try:
+            out["write_errors"] = write_error_leg(ctx)
+            log(f"write errors: {out['write_errors']['designs_per_s']:.3g} designs/s in lock step")
+        except Exception as e:
+            out["write_errors"] = {"error": repr(e)}
     if args.thermal > 0:
         try:
             out["thermal"] = thermal_leg(ctx, thermal_meshes, steps=args.thermal_steps)
