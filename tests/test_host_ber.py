@@ -174,3 +174,17 @@ def test_lock_step_searches_match_the_single_design_driver():
     longest = max(len(w.targ.levels) for w in singles) + max(len(w.prev.levels) for w in singles if w.prev)
     assert len(ctx.calls) == longest
     assert max(ctx.calls) == 12 * len(designs)
+
+
+def test_barrier_profile_refinement():
+    """The library driver's barrier from a chain profile: the parabola vertex is exact on a
+    parabola, an end maximum is taken as is, and the barrier is measured from the first image."""
+    from paper_1603_09493_amd import barrier as B
+    s = np.array([0.0, 0.5, 1.2, 1.9, 2.4, 3.1])
+    E = -2.0 * (s - 1.55) ** 2 + 7.0
+    assert abs(B.profile_barrier(s, E) - (7.0 - E[0])) < 1e-12
+    assert B.profile_barrier(s, -s) == 0.0
+    assert B.profile_barrier(s, s) == pytest.approx(3.1)
+    # Eq. (3): 130 GHz attempts during 1 ns, suppressed by the Boltzmann factor
+    assert B.ber_adj(0.0) == pytest.approx(130.0)
+    assert B.ber_adj(40 * 1.380649e-23 * 300) == pytest.approx(130.0 * math.exp(-40))
