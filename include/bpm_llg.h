@@ -306,8 +306,9 @@ typedef struct {
  * cand is read.  Work is queued on hip_stream (NULL = the context's stream).                   */
 int bpm_gp_ei(bpm_ctx* ctx, const bpm_gp* gp, int64_t m, double* cand, uint64_t seed, double* yhat,
               double* s, double* ei, void* hip_stream);
-/* Index of the largest of v [m] (device FP64, m >= 1), the lowest index among equal values (NaN
- * never wins), into idx (device int64 [1]); queued on hip_stream (NULL = the context's stream). */
+/* Index of the largest of v [m] (device FP64, m >= 1), the lowest index among equal values, into
+ * idx (device int64 [1]; -1 if every value is NaN, which never wins); queued on hip_stream (NULL =
+ * the context's stream).  Uses a small stream-ordered temporary allocation. */
 int bpm_argmax(bpm_ctx* ctx, const double* v, int64_t m, int64_t* idx, void* hip_stream);
 
 /* ------------------------------------------------------------------------------------------ */
