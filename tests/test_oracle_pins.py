@@ -451,3 +451,34 @@ def test_media_layout_density():
     tb_in2 = (0.0254 / 1e-9) ** 2 / cell_nm2 / 1e12
     assert round(tb_in2, 2) == dens
     assert round(math.pi * (d / 2) ** 2 / cell_nm2, 3) == fill
+
+
+def test_interface_areas_integrate_linear_fields(oracle_mod):
+    """The lumped interface areas a_p are vertex weights of the interface triangles (area / 3 per
+    vertex), so they integrate every linear function of (x, y) over the interface exactly: their
+    sum and first moments must equal those of the triangles, computed here from the triangles'
+    own areas and centroids (the triangles are the tet faces whose three nodes lie on the hard
+    side of the interface)."""
+    mesh = I.island_mesh(5e-9, 3.5e-9, 3e-9, 4e-9, 1.1e-9, seed=4)
+    om = oracle_mod.OracleMesh(mesh)
+    a = om.export()["aif"]
+    hard = set(int(q) for q in mesh.iface[:, 1])
+    P = mesh.xyz.T
+    faces = set()
+    for t in mesh.tet:
+        for drop in range(4):
+            f = tuple(sorted(int(t[k]) for k in range(4) if k != drop))
+            if all(v in hard for v in f):
+                faces.add(f)
+    A = np.array([0.5 * np.linalg.norm(np.cross(P[f[1]] - P[f[0]], P[f[2]] - P[f[0]])) for f in faces])
+    C = np.array([(P[f[0]] + P[f[1]] + P[f[2]]) / 3.0 for f in faces])
+    xy = P[mesh.iface[:, 1], :2]
+    assert abs(a.sum() - A.sum()) <= 1e-12 * A.sum()
+    for d in range(2):
+        ref = (A * C[:, d]).sum()
+        scale = A.sum() * np.abs(P[:, d]).max()
+        assert abs((a * xy[:, d]).sum() - ref) <= 1e-12 * scale, d
+    # a quadratic is not integrated exactly by vertex weights: the check above is not vacuous
+    q = (a * xy[:, 0] ** 2).sum()
+    qref = sum(Ai * (Ci[0] ** 2) for Ai, Ci in zip(A, C))
+    assert abs(q - qref) > 1e-6 * abs(qref)
