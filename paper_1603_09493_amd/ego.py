@@ -141,6 +141,10 @@ class Proposer:
         self.idx = torch.empty(1, dtype=torch.int64, device=dev)
 
     def evaluate(self, model: Model, f_min: float, seed: int):
+        """EI of `model` at m candidates drawn with Philox key `seed` (non-zero: seed 0 would make
+        the library read the candidate buffer instead of filling it)."""
+        if seed == 0:
+            raise ValueError("candidate seed must be non-zero")
         dm = DeviceModel(model, f_min)
         bpm.gp_ei(self.ctx, dm.desc, self.m, self.cand, self.ei, seed=seed, yhat=self.yhat, sd=self.sd)
         return dm
@@ -151,6 +155,8 @@ class Proposer:
         dm = self.evaluate(model, f_min, seed)
         bpm.argmax(self.ctx, self.ei, self.idx)
         k = int(self.idx.item())
+        if k < 0:
+            raise RuntimeError("expected improvement is NaN at every candidate")
         out = (self.cand[k].cpu().numpy().copy(), float(self.ei[k].item()), float(self.yhat[k].item()),
                float(self.sd[k].item()))
         torch.cuda.synchronize()
@@ -179,7 +185,10 @@ def optimise(ctx: bpm.Context, f, X0, iters: int, m: int = 1 << 18, seed: int = 
     """The loop of Sec. II.A: evaluate the start points, then fit, propose the largest-EI
     candidate, evaluate it, until iters points were added or the largest EI is <= ei_tol.
     f_many (optional) evaluates a list of points at once (the start design in one batch, and,
-    with q > 1, q kriging-believer proposals per step)."""
+    with q > 1, q kriging-believer proposals per step).  seed >= 1: step k draws its candidates
+    with Philox key seed + k (seed (seed + k) * 1000 + j for the j-th point of a batch)."""
+    if seed < 1:
+        raise ValueError("seed must be >= 1")
     X = np.array(X0, dtype=np.float64)
     t0 = time.perf_counter()
     y = np.array(f_many(list(X)) if f_many is not None else [f(x) for x in X], dtype=np.float64)
