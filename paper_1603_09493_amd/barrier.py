@@ -68,6 +68,8 @@ def string_barrier(ctx: bpm.Context, mid: int, n: int, mat, fld, chain, offset=(
     keeps the material's)."""
     chain = np.asarray(chain, dtype=np.float64)
     P = chain.shape[0]
+    if iters < 1 or not 3 <= P <= 64:
+        raise ValueError("need iters >= 1 and 3..64 images")
     if rtol is None:
         rtol = 1e-6 if precision == 64 else 1e-5
     if relax_alpha is not None:
@@ -118,6 +120,8 @@ def string_barrier_many(ctx: bpm.Context, mesh, mats, flds, chains, offsets, dta
     q = len(mats)
     chains = [np.asarray(c, dtype=np.float64) for c in chains]
     P = chains[0].shape[0]
+    if iters < 1 or not 3 <= P <= 64 or q < 1:
+        raise ValueError("need iters >= 1, 3..64 images and at least one string")
     if rtol is None:
         rtol = 1e-6 if precision == 64 else 1e-5
     mids = [] if mids is None else mids
