@@ -313,13 +313,16 @@ def patch_workload(seed: int = 1, n_target: int = 2000, sigma_rel: float = 0.05)
 
 # Recording geometry of the 4 Tb/in^2 media (Sec. II.B, Fig. 3) and of the write simulations
 # (Sec. II.C): pseudo-hexagonal islands, 13.5 nm down-track and 11.7 nm cross-track pitch, 12 nm
-# dots of 12 nm height (soft + 1 nm interlayer + hard), J_S = 0.7 T in both phases,
-# K_1,soft = 0.2 K_1,hard; the head moves at 13.5 m/s, so one bit period is 1 ns.
+# dots of 12 nm height (6 nm soft on top, 1 nm interlayer, 5 nm hard, as Fig. 3 labels them; the
+# middle of the soft phase then lies 9 nm below the air-bearing surface at 6 nm spacing),
+# J_S = 0.7 T in both phases, K_1,soft = 0.2 K_1,hard; the head moves at 13.5 m/s, so one bit
+# period is 1 ns.
 MEDIA_PITCH_DOWN = 13.5 * NM
 MEDIA_PITCH_CROSS = 11.7 * NM
 MEDIA_DOT = 12.0 * NM
 MEDIA_INTERLAYER = 1.0 * NM
-MEDIA_LAYER = 0.5 * (12.0 * NM - MEDIA_INTERLAYER)      # soft and hard thickness (equal split)
+MEDIA_SOFT = 6.0 * NM
+MEDIA_HARD = 5.0 * NM
 MEDIA_JS = 0.7                                          # tesla
 HEAD_VELOCITY = 13.5                                    # m/s, down-track (+x)
 BIT_PERIOD = MEDIA_PITCH_DOWN / HEAD_VELOCITY           # 1 ns
@@ -336,8 +339,8 @@ def recording_layout(p_down: float = MEDIA_PITCH_DOWN, p_cross: float = MEDIA_PI
             "adjacent": (0.5 * p_down, p_cross, 0.0)}
 
 
-def media_mesh(n_target: int = 600, seed: int = 0, d: float = MEDIA_DOT, t_soft: float = MEDIA_LAYER,
-               t_hard: float = MEDIA_LAYER) -> Mesh:
+def media_mesh(n_target: int = 600, seed: int = 0, d: float = MEDIA_DOT, t_soft: float = MEDIA_SOFT,
+               t_hard: float = MEDIA_HARD) -> Mesh:
     """One cylindrical island of the media (hard layer z in [0, t_hard], soft on top)."""
     return island_mesh_target(0.5 * d, 0.5 * d, t_soft, t_hard, n_target, seed=seed)
 
@@ -382,7 +385,7 @@ def default_head_grid(B_peak: float = 2.2, psi_deg: float = 25.0):
     sampled over [-40, 50] x [-30, 30] x [-2.5, 15] nm."""
     psi = math.radians(psi_deg)
     d = (math.sin(psi), 0.0, -math.cos(psi))
-    return write_head_grid(B_peak, d, 4 * NM, 10 * NM, 10 * NM, 2 * MEDIA_LAYER, 25 * NM,
+    return write_head_grid(B_peak, d, 4 * NM, 10 * NM, 10 * NM, MEDIA_SOFT + MEDIA_HARD, 25 * NM,
                            lo=(-40 * NM, -30 * NM, -2.5 * NM), hi=(50 * NM, 30 * NM, 15 * NM))
 
 
