@@ -310,7 +310,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--slice-ps", type=float, default=15.0, help="simulated time per step (ps)")
     ap.add_argument("--islands", type=int, default=4096)
-    ap.add_argument("--budget-s", type=float, default=470.0,
+    ap.add_argument("--budget-s", type=float, default=500.0,
                     help="wall-clock budget of the whole process; stepping stops early to keep it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -452,9 +452,9 @@ def main():
 
     signal.signal(signal.SIGTERM, on_term)
     # wall time kept for what follows the timed steps (measured: surrogate ~10 s, thermal leg
-    # ~3 s, oracle sample ~15 s, write-error leg ~20 s), with margin
+    # ~3 s, oracle sample ~15 s, write-error leg ~41 s), with margin
     reserve = (20.0 + (0.0 if args.no_surrogate else 25.0) + (0.0 if args.no_cpu_baseline else 30.0)
-               + (0.0 if args.thermal <= 0 else 10.0 + 0.1 * args.thermal) + (0.0 if args.no_ber else 40.0))
+               + (0.0 if args.thermal <= 0 else 10.0 + 0.1 * args.thermal) + (0.0 if args.no_ber else 60.0))
     stop = None
     t_step = None
     for k in range(args.steps):
