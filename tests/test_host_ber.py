@@ -140,6 +140,29 @@ def test_recording_layout_is_pseudo_hexagonal():
     assert abs(I.BIT_PERIOD - 1e-9) < 1e-21
 
 
+def test_media_island_layers():
+    """The media island of Fig. 3: a 12 nm cylinder, 6 nm soft phase on top of a 5 nm hard phase,
+    the two coupled across the 1 nm interlayer (not meshed): layer extents, the interface plane
+    with one partner per interface node, and layer volumes in the ratio 6 : 5."""
+    mesh = I.media_mesh(n_target=300)
+    z, lay = mesh.xyz[2], mesh.layer
+    r = np.hypot(mesh.xyz[0], mesh.xyz[1])
+    assert r.max() <= 6e-9 * (1 + 1e-12) and r.max() > 5.9e-9
+    assert np.isclose(z[lay == 1].min(), 0.0) and np.isclose(z[lay == 1].max(), 5e-9)
+    assert np.isclose(z[lay == 0].min(), 5e-9) and np.isclose(z[lay == 0].max(), 11e-9)
+    s, h = mesh.iface[:, 0], mesh.iface[:, 1]
+    assert np.all(lay[s] == 0) and np.all(lay[h] == 1)
+    assert np.allclose(mesh.xyz[:, s], mesh.xyz[:, h]) and np.allclose(z[s], 5e-9)
+    assert len(np.unique(s)) == len(s) == len(np.unique(h))
+    assert abs(I.media_material().delta_int - 1e-9) < 1e-21
+    p = mesh.xyz[:, mesh.tet]                                # [3][ntet][4]
+    vol = np.abs(np.einsum("ij,ij->j", np.cross(p[:, :, 1] - p[:, :, 0], p[:, :, 2] - p[:, :, 0], axis=0),
+                           p[:, :, 3] - p[:, :, 0])) / 6.0
+    soft = lay[mesh.tet].max(axis=1) == 0
+    assert np.all(lay[mesh.tet][~soft] == 1)               # no tetrahedron straddles the interface
+    assert abs(vol[soft].sum() / vol[~soft].sum() - 6.0 / 5.0) < 1e-9
+
+
 def test_lock_step_searches_match_the_single_design_driver():
     """write_errors_many over designs whose head strengths differ gives, design by design, the
     result of write_errors, in as many launches as the longest single search needs."""
