@@ -227,9 +227,9 @@ def ego_ei_leg(ctx, n=128, d=4, m=1 << 22, reps=5):
     flops = m * (n * (3 * d + 2) + n * (n + 1) + 6 * n + 40)
     del dm
     return {"n_train": n, "d": d, "candidates": m, "ms_per_call": ms, "candidates_per_s": m / ms * 1e3,
-            "fit_s": fit_s, "bound": "alu", "achieved_tflops": flops / ms / 1e9,
+            "fit_s": fit_s, "bound": "mfma", "achieved_tflops": flops / ms / 1e9,
             "peak_tflops": roofline.MI355X_FP64_TFLOPS, "frac": flops / ms / 1e9 / roofline.MI355X_FP64_TFLOPS,
-            "kernel": "gp_ei_kernel + argmax (FP64 vector FMA; peak: FP64 78.6 TFLOP/s)"}
+            "kernel": "gp_ei_kernel + argmax (L^-1 r on FP64 matrix cores, 16x16x4; peak: FP64 78.6 TFLOP/s)"}
 
 
 def write_error_leg(ctx, designs=16, nodes=300):

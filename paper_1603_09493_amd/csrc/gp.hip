@@ -7,10 +7,11 @@
 //   q = |v_0..n-1|^2 = r' R^-1 r,   yhat = mu + v_n,   p = v_{n+1} = 1' R^-1 r,
 //   s^2 = sigma^2 (1 - q + (1 - p)^2 / c),  c = 1' R^-1 1,
 //   EI = (f_min - yhat) Phi(z) + s phi(z),  z = (f_min - yhat) / s.
-// For a block of 64 candidates that product is a 64 x n by n x (n + 2) matrix product: 256
-// threads hold 4 candidates x 4 rows of G each, the correlations are formed while a 16-column
-// slice of them is staged in LDS, and only the lower triangle of L^-1 is visited; two row tiles
-// share each staged slice, and alpha' r and w' r are summed while the correlations are formed.
+// For a block of 64 candidates, L^-1 times their correlations is an n x n by n x 64 matrix
+// product, done on the FP64 matrix cores (16 x 16 x 4 steps): each of the four waves owns 16
+// candidates and every 16-row tile of a 128-row pass, the correlations are formed while a
+// 16-column slice of them is staged in LDS beside the same columns of L^-1, and tiles wholly above
+// the diagonal of L^-1 are skipped; alpha' r and w' r are summed while the correlations are formed.
 // FP64 throughout (the variance is a difference of nearly equal terms near training points).
 #include <hip/hip_runtime.h>
 
@@ -25,19 +26,27 @@ namespace bpm {
 namespace {
 
 constexpr int kGpBS = 256;
-constexpr int kGpC = 64;      // candidates per block
-constexpr int kGpK = 16;      // columns of G per LDS stage
-constexpr int kGpTiles = 2;   // 64-row tiles of L^-1 per pass over the correlations
+constexpr int kGpC = 64;              // candidates per block, 16 per wave
+constexpr int kGpK = 16;              // columns of G per LDS stage
+constexpr int kGpRT = 8;              // 16-row tiles of L^-1 per pass over the correlations
+constexpr int kGpRows = 16 * kGpRT;
 static_assert(kGpBS == 4 * kGpC, "four threads form the correlations of each candidate");
+static_assert(kGpK % 4 == 0, "a stage is a whole number of 4-deep matrix-core steps");
 
-__global__ __launch_bounds__(kGpBS) void gp_ei_kernel(GpArgs a, long m, double* __restrict__ cand,
+typedef double gp_d4 __attribute__((ext_vector_type(4)));
+
+// At three or more waves per SIMD the compiler keeps the 32 accumulators of a lane in ordinary
+// vector registers (126 in all, four waves per SIMD) instead of 118 + 64 accumulation registers
+// (two waves); the extra waves hide the LDS and L2 latency of the staging, 1.4x faster.
+__global__ __launch_bounds__(kGpBS) __attribute__((amdgpu_waves_per_eu(3, 8))) void gp_ei_kernel(GpArgs a, long m, double* __restrict__ cand,
                                                       uint64_t seed, double* __restrict__ yhat,
                                                       double* __restrict__ sd, double* __restrict__ ei) {
   __shared__ double xc[kGpC][kMaxGpDim];
   __shared__ double Rt[kGpK][kGpC + 1];
-  __shared__ double Gt[kGpTiles][kGpC][kGpK + 1];
+  __shared__ double Gt[kGpRows][kGpK + 1];
   __shared__ double th[kMaxGpDim];
   __shared__ double red[2][kGpBS];
+  __shared__ double qs[kGpC];
   const int t = threadIdx.x;
   const long c0 = (long)blockIdx.x * kGpC;
   const int d = a.d, n = a.n;
@@ -60,20 +69,26 @@ __global__ __launch_bounds__(kGpBS) void gp_ei_kernel(GpArgs a, long m, double* 
     }
     xc[cc][l] = x;
   }
-  const int cs = t >> 4, rs = t & 15;    // candidates 4 cs .. 4 cs + 3, rows 4 rs .. 4 rs + 3 of a tile
+  // matrix-core operands: A = 16 rows x 4 columns of L^-1 (lane: row li, column lk), B = 4
+  // columns x 16 candidates of the correlations (lane: column lk, candidate li); the 16 x 16 result
+  // leaves rows 4 lk .. 4 lk + 3 of candidate li in each lane
+  const int lane = t & 63, wv = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int ccr = t & (kGpC - 1);        // the candidate whose correlations this thread forms
   const double* alpha = a.G + (size_t)n * n;
-  const double* wv = a.G + (size_t)(n + 1) * n;
-  double qa[4] = {0, 0, 0, 0};
+  const double* wv_ = a.G + (size_t)(n + 1) * n;
+  double qa = 0.0;                       // |L^-1 r|^2 of candidate 16 wv + li, partial over rows
   double ya = 0.0, pa = 0.0;             // alpha' r and w' r of candidate ccr, partial over its j
-  const int nt = (n + kGpC - 1) / kGpC;  // 64-row tiles of L^-1
-  for (int p0 = 0; p0 < nt; p0 += kGpTiles) {
-    const int p1 = min(p0 + kGpTiles, nt);
-    const bool last = p1 == nt;
-    // rows of L^-1 below 64 p1 have no entries beyond column 64 p1 - 1; the last pass also forms
-    // alpha' r and w' r, so it covers every column
-    const int kmax = last ? n : kGpC * p1;
-    double acc[kGpTiles][4][4] = {};
+  const int np = (n + kGpRows - 1) / kGpRows;   // 128-row passes
+  for (int p = 0; p < np; ++p) {
+    const int r0 = kGpRows * p;
+    const bool last = p == np - 1;
+    // rows of L^-1 below r0 + 128 have no entries beyond column r0 + 127; the last pass also
+    // forms alpha' r and w' r, so it covers every column
+    const int kmax = last ? n : r0 + kGpRows;
+    gp_d4 acc[kGpRT];
+#pragma unroll
+    for (int q = 0; q < kGpRT; ++q) acc[q] = gp_d4{0.0, 0.0, 0.0, 0.0};
     for (int j0 = 0; j0 < kmax; j0 += kGpK) {
       __syncthreads();
       for (int e = t; e < kGpK * kGpC; e += kGpBS) {
@@ -89,65 +104,54 @@ __global__ __launch_bounds__(kGpBS) void gp_ei_kernel(GpArgs a, long m, double* 
           r = exp(-s);
           if (last) {
             ya = fma(alpha[j], r, ya);
-            pa = fma(wv[j], r, pa);
+            pa = fma(wv_[j], r, pa);
           }
         }
         Rt[jj][cc] = r;
       }
-      for (int e = t; e < (p1 - p0) * kGpC * kGpK; e += kGpBS) {
-        const int tl = e / (kGpC * kGpK), rem = e - tl * (kGpC * kGpK);
-        const int ii = rem / kGpK, jj = rem - ii * kGpK;
-        const int i = kGpC * (p0 + tl) + ii, j = j0 + jj;
-        Gt[tl][ii][jj] = (i < n && j < n) ? a.G[(size_t)i * n + j] : 0.0;
+      for (int e = t; e < kGpRows * kGpK; e += kGpBS) {
+        const int ii = e / kGpK, jj = e - ii * kGpK;
+        const int i = r0 + ii, j = j0 + jj;
+        Gt[ii][jj] = (i < n && j < n) ? a.G[(size_t)i * n + j] : 0.0;
       }
       __syncthreads();
 #pragma unroll
-      for (int tl = 0; tl < kGpTiles; ++tl) {
-        if (p0 + tl >= p1 || j0 >= kGpC * (p0 + tl + 1)) continue;   // beyond this tile's triangle
-#pragma unroll 4
-        for (int jj = 0; jj < kGpK; ++jj) {
-          double rv[4], gv[4];
+      for (int s4 = 0; s4 < kGpK / 4; ++s4) {
+        const int jk = j0 + 4 * s4;      // first column of this step
+        const double bv = Rt[4 * s4 + lk][16 * wv + li];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) rv[u] = Rt[jj][4 * cs + u];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) gv[u] = Gt[tl][4 * rs + u][jj];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[tl][u][v] = fma(rv[u], gv[v], acc[tl][u][v]);
+        for (int q = 0; q < kGpRT; ++q) {
+          const int rlo = r0 + 16 * q;
+          // (wave-uniform) rows past n, or columns wholly above this tile's part of the triangle
+          if (rlo >= n || jk > rlo + 15) continue;
+          const double av = Gt[16 * q + li][4 * s4 + lk];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
         }
       }
     }
+    // rows at or past n hold zeros (their rows of G were staged as zeros)
 #pragma unroll
-    for (int tl = 0; tl < kGpTiles; ++tl)
+    for (int q = 0; q < kGpRT; ++q)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = kGpC * (p0 + tl) + 4 * rs + v;
-        if (p0 + tl < p1 && i < n)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) qa[u] = fma(acc[tl][u][v], acc[tl][u][v], qa[u]);
-      }
+      for (int r = 0; r < 4; ++r) qa = fma(acc[q][r], acc[q][r], qa);
   }
-  // |L^-1 r|^2: sums over the 16 threads (rs) that share a candidate quartet (lanes 16 cs ..)
-#pragma unroll
-  for (int w = 8; w >= 1; w >>= 1)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) qa[u] += __shfl_xor(qa[u], w, 16);
+  // |L^-1 r|^2: sums over the four lane groups (lk) that hold rows of the same candidate
+  qa += __shfl_xor(qa, 16);
+  qa += __shfl_xor(qa, 32);
   // alpha' r and w' r: sums over the four threads that formed correlations of one candidate
   red[0][t] = ya;
   red[1][t] = pa;
+  if (lk == 0) qs[16 * wv + li] = qa;
   __syncthreads();
-  if (rs == 0) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int cl = 4 * cs + u;
-      const long c = c0 + cl;
-      if (c >= m) continue;
+  if (t < kGpC) {
+    const int cl = t;
+    const long c = c0 + cl;
+    if (c < m) {
       const double yv = red[0][cl] + red[0][cl + 64] + red[0][cl + 128] + red[0][cl + 192];
       const double pv = red[1][cl] + red[1][cl + 64] + red[1][cl + 128] + red[1][cl + 192];
       const double mu = a.mu + yv;
       const double one_p = 1.0 - pv;
-      const double var = a.sigma2 * (1.0 - qa[u] + one_p * one_p / a.c);
+      const double var = a.sigma2 * (1.0 - qs[cl] + one_p * one_p / a.c);
       const double s = var > 0.0 ? sqrt(var) : 0.0;
       const double imp = a.f_min - mu;
       double e;
