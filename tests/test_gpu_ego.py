@@ -2,8 +2,8 @@
 
 bpm_gp_ei: candidates bit-identical to the oracle's own Philox draw, predictor to 1e-9 relative,
 error-estimate and EI to 1e-6 of the process standard deviation (the variance is a difference of
-nearly equal terms), argmax on the largest EI; shapes with ragged 64-candidate blocks, one and
-several 64-row tiles of the model, d = 1 and 16.  The loop then finds the Branin minimum, and runs
+nearly equal terms), argmax on the largest EI; shapes with ragged 64-candidate blocks, one, two
+and three 128-row passes over L^-1 (the last one ragged), d = 1 and 16.  The loop then finds the Branin minimum, and runs
 with the write-error judge."""
 import math
 
@@ -30,7 +30,8 @@ def _oracle_candidates(O, seed, m, d):
 # the library's host side through its Cholesky factor, and with cond(R) ~ 1e12 (130 points in 2-D
 # at theta ~ 1) those two roundings alone already differ by ~1e-9 in the predictor
 @pytest.mark.parametrize("n,d,m,th", [(37, 4, 20011, (0.5, 5.0)), (130, 2, 5000, (20.0, 200.0)),
-                                      (1, 1, 77, (0.5, 5.0)), (70, 16, 1000, (0.5, 5.0))])
+                                      (1, 1, 77, (0.5, 5.0)), (70, 16, 1000, (0.5, 5.0)),
+                                      (300, 4, 3001, (5.0, 50.0))])
 def test_gp_ei_matches_oracle(oracle_mod, n, d, m, th):
     import torch
     from oracle import ego as OE
