@@ -41,7 +41,8 @@ typedef double gp_d4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(kGpBS) __attribute__((amdgpu_waves_per_eu(3, 8))) void gp_ei_kernel(GpArgs a, long m, double* __restrict__ cand,
                                                       uint64_t seed, double* __restrict__ yhat,
                                                       double* __restrict__ sd, double* __restrict__ ei) {
-  __shared__ double xc[kGpC][kMaxGpDim];
+  __shared__ double xc[kGpC][kMaxGpDim + 1];   // odd row stride: the 64 candidates of a wave
+                                               // read one coordinate each from different banks
   __shared__ double Rt[kGpK][kGpC + 1];
   __shared__ double Gt[kGpRows][kGpK + 1];
   __shared__ double th[kMaxGpDim];
